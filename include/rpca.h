@@ -1,0 +1,174 @@
+/*
+ * rpca.h - C ABI of librpca: accelerated alternating projections (AccAltProj)
+ * for fully observed robust PCA, D = L + S, on AMD Instinct MI355X (gfx950).
+ *
+ * The method is Algorithm 1 (AccAltProj loop), Algorithm 2 (Trim) and
+ * Algorithm 3 (initialisation by two steps of modified AltProj) of Cai, Cai and
+ * Wei, "Accelerated Alternating Projections for Robust Principal Component
+ * Analysis", with the fast SVD of the tangent-space projection of Section 2.1
+ * and the stopping rule err_k < tol of Section 3.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are row-major. D is m x n with row stride ldd >= n elements.
+ *   Its element type is params->dtype (RPCA_F64: double, RPCA_F32: float).
+ * - Pointers documented as "device" must point to memory of the current HIP
+ *   device (hipMalloc / torch CUDA tensors). "host" pointers are ordinary host
+ *   memory. The library never allocates, frees or retains caller buffers.
+ * - The iterate factors are FP64 whatever the dtype of D: U is m x r (row
+ *   stride r), V is n x r (row stride r), sigma has r entries, so that
+ *   L_k = U diag(sigma) V^T. S_k is never stored: it is T_zeta_k(D - L_k).
+ * - ws / ws_bytes is a caller-owned device workspace of at least the size
+ *   rpca_workspace_size() reports, 256-byte aligned. Its content does not need
+ *   to be initialised and is not meaningful after a call.
+ * - stream is a hipStream_t (0 = the null stream). Every device operation is
+ *   ordered on it. Calls that report host-visible results (the scalars of
+ *   rpca_state, histories) synchronise with the stream before returning.
+ * - One call at a time per workspace; calls sharing a workspace must not
+ *   overlap. Calls with distinct workspaces may run concurrently.
+ * - Return value: RPCA_OK (0) or RPCA_MAXITER (1) on success, a negative
+ *   RPCA_E* code on failure. Arguments are validated before any launch; a
+ *   failed validation leaves every output untouched.
+ */
+#ifndef RPCA_H
+#define RPCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define RPCA_OK           0   /* success                                               */
+#define RPCA_MAXITER      1   /* rpca_solve ran max_iter iterations without err < tol  */
+#define RPCA_EINVAL      -1   /* bad shape, parameter, pointer or alignment            */
+#define RPCA_EWORKSPACE  -2   /* workspace missing or smaller than required            */
+#define RPCA_EHIP        -3   /* a HIP runtime call failed (see rpca_last_hip_error)   */
+#define RPCA_ENODEV      -4   /* no gfx950 device is current                           */
+
+/* ---- element types of D ------------------------------------------------ */
+#define RPCA_F64 0            /* D (and dense L/S outputs) are double                  */
+#define RPCA_F32 1            /* D (and dense L/S outputs) are float                   */
+
+/* ---- flags ------------------------------------------------------------- */
+#define RPCA_FLAG_NO_TRIM 1u  /* AccAltProj without trim (Section 3): U~ = U_k, V~ = V_k */
+
+/* Largest supported rank r and init block p. */
+#define RPCA_MAX_RANK 16
+
+typedef struct rpca_params {
+    int64_t  m, n;         /* D is m x n, 2r <= min(m, n)                                    */
+    int64_t  ldd;          /* row stride of D in elements, ldd >= n                          */
+    int32_t  r;            /* target rank, 1 <= r <= RPCA_MAX_RANK                           */
+    int32_t  dtype;        /* RPCA_F64 or RPCA_F32                                           */
+    double   beta;         /* threshold parameter of Algorithm 1 (> 0)                       */
+    double   beta_init;    /* threshold parameter of Algorithm 3 (> 0)                       */
+    double   gamma;        /* convergence-rate parameter, 0 <= gamma < 1 (Section 2.1)       */
+    double   mu;           /* Trim level of Algorithm 2 (> 0 unless RPCA_FLAG_NO_TRIM)        */
+    double   tol;          /* stop when err_k < tol (Section 3), tol > 0                     */
+    int32_t  max_iter;     /* iteration cap; the paper uses 100 (Section 3)                  */
+    int32_t  init_block;   /* p: columns of the initial truncated-SVD iteration,
+                              r <= p <= RPCA_MAX_RANK and 2p <= min(m, n); 0 = default     */
+    int32_t  init_max_passes; /* cap on passes over D per init stage; 0 = default (40)      */
+    uint32_t flags;        /* RPCA_FLAG_*                                                    */
+    uint64_t seed;         /* seeds the start block of the initial truncated SVD             */
+} rpca_params;
+
+/* Iterate (L_k, S_k): L_k = U diag(sigma) V^T, S_k = T_zeta(D - L_k). The three
+ * arrays are caller-owned device memory; the scalars are host values. */
+typedef struct rpca_state {
+    double  *U;            /* device, m x r, row stride r                                    */
+    double  *V;            /* device, n x r, row stride r                                    */
+    double  *sigma;        /* device, r                                                      */
+    double   zeta;         /* zeta_k                                                         */
+    double   err;          /* err_k = ||D - L_k - S_k||_F / ||D||_F (Section 3)               */
+    double   sigma1_pt;    /* sigma_1 of the P_T(D - S_{k-1}) that produced L_k (0 at k = 0) */
+    double   sigma_r1_pt;  /* sigma_{r+1} of that matrix                                     */
+    double   normD;        /* ||D||_F; set by rpca_init / rpca_solve. rpca_step reuses it
+                              when > 0 and otherwise spends one extra pass computing it      */
+    int32_t  k;            /* iteration index                                                */
+    int32_t  init_passes;  /* passes over D spent by rpca_init (diagnostic)                  */
+} rpca_state;
+
+/* Bytes of device workspace needed by every entry point for these params.
+ * Returns RPCA_EINVAL for invalid params (bytes untouched). */
+int rpca_workspace_size(const rpca_params *p, size_t *bytes);
+
+/* Algorithm 3. zeta_{-1} = beta_init sigma_1(D); S_{-1} = T(D);
+ * L_0 = H_r(D - S_{-1}) by a block two-sided subspace iteration run to
+ * convergence; zeta_0 = beta sigma_1(D - S_{-1}); S_0 = T_zeta_0(D - L_0).
+ * D: device m x n (dtype). On return st holds L_0 (U, sigma, V), zeta_0, err_0
+ * and k = 0. */
+int rpca_init(const void *D, const rpca_params *p, rpca_state *st,
+              void *ws, size_t ws_bytes, void *stream);
+
+/* Algorithm 2 followed by orthonormalisation: U_tilde (device m x r) and
+ * V_tilde (device n x r), FP64, row stride r, are orthonormal bases of the
+ * trimmed factors A = Trim(U), B = Trim(V) of L_k (footnote to Section 2.1).
+ * With RPCA_FLAG_NO_TRIM they span U_k and V_k. st is read only. */
+int rpca_trim(const rpca_params *p, const rpca_state *st,
+              double *U_tilde, double *V_tilde,
+              void *ws, size_t ws_bytes, void *stream);
+
+/* One body of Algorithm 1 from any state k: Trim, L_{k+1} = H_r(P_T(D - S_k))
+ * through the 2r x 2r matrix of Section 2.1, zeta_{k+1}, S_{k+1} implicit and
+ * err_{k+1}. Reads st (U, sigma, V, zeta, k) and overwrites it with state k+1.
+ * Costs two passes over D. */
+int rpca_step(const void *D, const rpca_params *p, rpca_state *st,
+              void *ws, size_t ws_bytes, void *stream);
+
+/* Algorithm 3 then Algorithm 1 until err_k < tol or k = max_iter, one fused
+ * pass over D per iteration. err_hist / zeta_hist (host, nullable) receive
+ * err_0..err_K and zeta_0..zeta_K, at most hist_cap entries each. Returns
+ * RPCA_OK if err_K < tol, RPCA_MAXITER otherwise; st holds the final state. */
+int rpca_solve(const void *D, const rpca_params *p, rpca_state *st,
+               double *err_hist, double *zeta_hist, int32_t hist_cap,
+               void *ws, size_t ws_bytes, void *stream);
+
+/* Dense outputs of Algorithm 1: L_out = U diag(sigma) V^T (row stride ldl) and
+ * S_out = T_zeta(D - L) (row stride lds), dtype elements, device. Either
+ * pointer may be NULL. st is read only. */
+int rpca_materialize(const void *D, const rpca_params *p, const rpca_state *st,
+                     void *L_out, int64_t ldl, void *S_out, int64_t lds,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* The dominant pass of one iteration, exposed for testing and measurement:
+ * with L = A_L B_L^T (A_L device m x r, B_L device n x r, FP64, row stride r),
+ * x = D - L, S = T_zeta(x) and Z = D - S (Section 2.1),
+ *   Y1 = Z V_t   (device m x r, FP64)    Y2 = Z^T U_t (device n x r, FP64)
+ *   *resid2 = sum over |x_ij| <= zeta of x_ij^2   (host scalar),
+ * where U_t (m x r) and V_t (n x r) are device FP64 bases. Inputs are rounded
+ * to dtype before the pass, as inside rpca_step. */
+int rpca_tangent_products(const void *D, const rpca_params *p,
+                          const double *A_L, const double *B_L, double zeta,
+                          const double *U_t, const double *V_t,
+                          double *Y1, double *Y2, double *resid2,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* Measurement of the dominant kernel. While enabled (process-wide), every
+ * streaming pass over D (the only kernel reading the m x n data) is bracketed
+ * by two HIP events recorded on the caller's stream; a pass queued after a
+ * loop has stopped, which does no work, is not counted. rpca_profile_read
+ * waits for the recorded passes and returns their summed duration in ms and
+ * their number since the previous read, then resets both. Disabling keeps
+ * the totals for a final read. Intended for benchmarks: the events add a few
+ * microseconds of queue work per pass. */
+int rpca_profile_enable(int on);
+int rpca_profile_read(double *stream_ms, int64_t *stream_launches);
+
+/* Static description of a status code. */
+const char *rpca_strerror(int status);
+
+/* hipError_t of the last failed HIP call on the calling thread (0 if none). */
+int rpca_last_hip_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int rpca_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPCA_H */

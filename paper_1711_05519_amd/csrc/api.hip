@@ -1,0 +1,708 @@
+// C ABI of librpca (include/rpca.h): argument validation, workspace layout and
+// the stream-ordered orchestration of the kernels in stream.hip / panel.hip.
+//
+// One iteration of the loop ("body") is five launches on the caller's stream:
+//   stream (one pass over D) -> gather -> complement -> update -> basis.
+// The host keeps one body queued ahead of the GPU and reads the stopping
+// decision, which the gather kernel publishes in mapped pinned memory, one body
+// late; bodies queued past the stop become no-ops on the device (Ctrl gating),
+// so the GPU never waits for the host and the host never blocks per iteration.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/rpca.h"
+#include "launch.hpp"
+
+using namespace rpca;
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+constexpr int DEFAULT_INIT_MAX_PASSES = 40;
+constexpr int MAX_DEVICES = 64;
+
+#define HIP_TRY(expr)                                    \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) {                          \
+            g_last_hip_error = (int)e_;                  \
+            return RPCA_EHIP;                            \
+        }                                                \
+    } while (0)
+
+#define RPCA_TRY(expr)              \
+    do {                            \
+        int s_ = (expr);            \
+        if (s_ < 0) return s_;      \
+    } while (0)
+
+struct DeviceInfo {
+    bool checked = false;
+    bool ok = false;
+    int cus = 256;
+    HostStatus* status_host = nullptr;
+    HostStatus* status_dev = nullptr;
+};
+std::mutex g_dev_mutex;
+DeviceInfo g_dev[MAX_DEVICES];
+
+int device_info(DeviceInfo** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return RPCA_ENODEV;
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    DeviceInfo& d = g_dev[dev];
+    if (!d.checked) {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev));
+        d.checked = true;
+        d.ok = std::string(prop.gcnArchName).find("gfx950") != std::string::npos;
+        d.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        if (d.ok) {
+            void* h = nullptr;
+            HIP_TRY(hipHostMalloc(&h, sizeof(HostStatus), hipHostMallocMapped | hipHostMallocCoherent));
+            memset(h, 0, sizeof(HostStatus));
+            void* dp = nullptr;
+            HIP_TRY(hipHostGetDevicePointer(&dp, h, 0));
+            d.status_host = static_cast<HostStatus*>(h);
+            d.status_dev = static_cast<HostStatus*>(dp);
+        }
+    }
+    if (!d.ok) return RPCA_ENODEV;
+    *out = &d;
+    return RPCA_OK;
+}
+
+bool is_fin(double x) { return isfinite(x) != 0; }
+
+// ---- measurement: events around every streaming pass ---------------------------
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;                        // free events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    double ms = 0.0;
+    int64_t launches = 0;
+};
+Profiler g_prof;
+
+hipEvent_t prof_event() {
+    if (!g_prof.pool.empty()) {
+        hipEvent_t e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int prof_collect_locked() {
+    for (auto& pr : g_prof.pending) {
+        HIP_TRY(hipEventSynchronize(pr.second));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second));
+        g_prof.ms += t;
+        g_prof.launches += 1;
+        g_prof.pool.push_back(pr.first);
+        g_prof.pool.push_back(pr.second);
+    }
+    g_prof.pending.clear();
+    return RPCA_OK;
+}
+
+// Launch of the streaming pass, bracketed by events when profiling is on.
+int stream_launch(const StreamArgs& a, int K, int dtype, bool rebuild, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g_prof.on) {
+        if (g_prof.pending.size() >= 4096) RPCA_TRY(prof_collect_locked());
+        e0 = prof_event();
+        e1 = prof_event();
+        if (!e0 || !e1) return RPCA_EHIP;
+        HIP_TRY(hipEventRecord(e0, s));
+    }
+    HIP_TRY(launch_stream(a, K, dtype, rebuild, s));
+    if (g_prof.on) {
+        HIP_TRY(hipEventRecord(e1, s));
+        g_prof.pending.emplace_back(e0, e1);
+    }
+    return RPCA_OK;
+}
+
+// The last queued body of a loop ran past the stop and did no work: drop its pass.
+void prof_drop_last() {
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    if (g_prof.on && !g_prof.pending.empty()) {
+        auto pr = g_prof.pending.back();
+        g_prof.pending.pop_back();
+        (void)hipEventSynchronize(pr.second);
+        g_prof.pool.push_back(pr.first);
+        g_prof.pool.push_back(pr.second);
+    }
+}
+
+int init_block_of(const rpca_params* p) {
+    if (p->init_block > 0) return p->init_block;
+    int q = p->r + 4;
+    if (q > KMAX) q = KMAX;
+    const int64_t lim = (p->m < p->n ? p->m : p->n) / 2;
+    if (q > lim) q = (int)lim;
+    return q < p->r ? p->r : q;
+}
+
+int validate(const rpca_params* p) {
+    if (!p) return RPCA_EINVAL;
+    if (p->m < 1 || p->n < 1 || p->m > (int64_t)INT32_MAX / 2 || p->n > (int64_t)INT32_MAX / 2) return RPCA_EINVAL;
+    if (p->ldd < p->n) return RPCA_EINVAL;
+    if (p->r < 1 || p->r > KMAX || 2 * (int64_t)p->r > (p->m < p->n ? p->m : p->n)) return RPCA_EINVAL;
+    if (p->dtype != RPCA_F64 && p->dtype != RPCA_F32) return RPCA_EINVAL;
+    if (!is_fin(p->beta) || !(p->beta > 0) || !is_fin(p->beta_init) || !(p->beta_init > 0)) return RPCA_EINVAL;
+    if (!is_fin(p->gamma) || p->gamma < 0 || p->gamma >= 1) return RPCA_EINVAL;
+    if (!is_fin(p->tol) || !(p->tol > 0)) return RPCA_EINVAL;
+    if (!(p->flags & RPCA_FLAG_NO_TRIM) && (!is_fin(p->mu) || !(p->mu > 0))) return RPCA_EINVAL;
+    if (p->max_iter < 0 || p->init_max_passes < 0) return RPCA_EINVAL;
+    if (p->flags & ~RPCA_FLAG_NO_TRIM) return RPCA_EINVAL;
+    if (p->init_block != 0) {
+        if (p->init_block < p->r || p->init_block > KMAX ||
+            2 * (int64_t)p->init_block > (p->m < p->n ? p->m : p->n))
+            return RPCA_EINVAL;
+    }
+    return RPCA_OK;
+}
+
+// Workspace layout: every region 256-byte aligned.
+struct Layout {
+    int K_main, K_init, KW;
+    int n_ct, n_rt_max, gU, gV;
+    size_t acc;                       // bytes of a partial (4 for FP32, 8 for FP64)
+    size_t elt;                       // bytes of an element of D
+    size_t off_ctrl, off_small, off_hist, off_P1, off_P2, off_resid, off_gpart;
+    size_t off_Y1, off_Y2, off_W1, off_W2, off_Ap, off_Bp, off_Unew, off_Vnew;
+    size_t off_Uf, off_Vf, off_AL, off_BL;
+    size_t total;
+};
+
+// The streaming pass runs one tile per resident workgroup (a single round, no
+// tail): the row tiling follows the kernel's occupancy on the device. The
+// workspace is sized for the largest tiling any device can ask for.
+constexpr int STREAM_MAX_SLOTS = 2048;   // 256 CUs x 8 workgroups of 256 threads
+constexpr int STREAM_MIN_TM = 64;
+
+int n_rt_for(int m, int n_ct, int slots) {
+    int n_rt = slots / n_ct;
+    if (n_rt < 1) n_rt = 1;
+    const int cap = (m + STREAM_MIN_TM - 1) / STREAM_MIN_TM;
+    return n_rt < cap ? n_rt : cap;
+}
+
+Layout make_layout(const rpca_params* p) {
+    Layout L;
+    L.K_main = p->r;
+    L.K_init = init_block_of(p);
+    L.KW = L.K_init > L.K_main ? L.K_init : L.K_main;
+    L.elt = p->dtype == RPCA_F32 ? 4 : 8;
+    L.acc = L.elt;
+    const int m = (int)p->m, n = (int)p->n;
+    L.n_ct = (n + STREAM_TN - 1) / STREAM_TN;
+    L.n_rt_max = n_rt_for(m, L.n_ct, STREAM_MAX_SLOTS);
+    L.gU = (m + PANEL_THREADS - 1) / PANEL_THREADS;
+    L.gV = (n + PANEL_THREADS - 1) / PANEL_THREADS;
+    const int rpb = PANEL_THREADS / GATHER_SPLIT;   // the gather kernel's workgroups own fewer rows
+    const int g_gather = (m + rpb - 1) / rpb + (n + rpb - 1) / rpb;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+    L.off_ctrl = take(sizeof(Ctrl));
+    L.off_small = take(sizeof(Small));
+    L.off_hist = take(2 * sizeof(double) * (size_t)(p->max_iter + 1));
+    L.off_P1 = take((size_t)L.n_ct * m * L.KW * L.acc);
+    L.off_P2 = take((size_t)L.n_rt_max * n * L.KW * L.acc);
+    L.off_resid = take(sizeof(double) * (size_t)L.n_ct * L.n_rt_max);
+    L.off_gpart = take(sizeof(double) * (size_t)(g_gather > L.gU + L.gV ? g_gather : L.gU + L.gV) * KMAX * KMAX);
+    const size_t pm = sizeof(double) * (size_t)m * L.KW, pn = sizeof(double) * (size_t)n * L.KW;
+    L.off_Y1 = take(pm); L.off_Y2 = take(pn);
+    L.off_W1 = take(pm); L.off_W2 = take(pn);
+    L.off_Ap = take(pm); L.off_Bp = take(pn);
+    L.off_Unew = take(pm); L.off_Vnew = take(pn);
+    const size_t tm = L.elt * (size_t)m * L.KW, tn = L.elt * (size_t)n * L.KW;
+    L.off_Uf = take(tm); L.off_Vf = take(tn);
+    L.off_AL = take(tm); L.off_BL = take(tn);
+    L.total = off;
+    return L;
+}
+
+// Everything one call needs: layout plus typed pointers into the workspace.
+struct Ctx {
+    const rpca_params* p;
+    Layout L;
+    char* ws;
+    hipStream_t s;
+    DeviceInfo* dev;
+    int dtype;
+    Ctrl* ctrl() const { return reinterpret_cast<Ctrl*>(ws + L.off_ctrl); }
+    Small* small() const { return reinterpret_cast<Small*>(ws + L.off_small); }
+    double* err_hist() const { return reinterpret_cast<double*>(ws + L.off_hist); }
+    double* zeta_hist() const { return err_hist() + (p->max_iter + 1); }
+    template <typename X> X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
+};
+
+int make_ctx(const rpca_params* p, void* ws, size_t ws_bytes, void* stream, Ctx* c) {
+    RPCA_TRY(validate(p));
+    DeviceInfo* dev = nullptr;
+    RPCA_TRY(device_info(&dev));
+    c->p = p;
+    c->L = make_layout(p);
+    if (!ws || ((uintptr_t)ws & 255u) != 0 || ws_bytes < c->L.total) return RPCA_EWORKSPACE;
+    c->ws = static_cast<char*>(ws);
+    c->s = static_cast<hipStream_t>(stream);
+    c->dev = dev;
+    c->dtype = p->dtype;
+    return RPCA_OK;
+}
+
+Ctrl base_ctrl(const Ctx& c, int stage, double zeta, int k, double normD2, int want_stop) {
+    const rpca_params* p = c.p;
+    Ctrl t;
+    memset(&t, 0, sizeof(t));
+    t.stage = stage;
+    t.k = k;
+    t.max_iter = p->max_iter;
+    t.r = p->r;
+    t.p = c.L.K_init;
+    t.keep = p->r;
+    t.init_max_passes = p->init_max_passes > 0 ? p->init_max_passes : DEFAULT_INIT_MAX_PASSES;
+    t.trim = (p->flags & RPCA_FLAG_NO_TRIM) ? 0 : 1;
+    t.want_stop = want_stop;
+    t.active = 1;
+    t.zeta = zeta;
+    t.normD2 = normD2;
+    t.beta = p->beta;
+    t.beta_init = p->beta_init;
+    t.gamma = p->gamma;
+    t.mu = p->mu;
+    t.tol = p->tol;
+    t.res_prev = 1e300;
+    t.tol_res_a = p->dtype == RPCA_F64 ? 1e-9 : 3e-6;
+    t.tol_res_b = p->dtype == RPCA_F64 ? 1e-13 : 3e-6;
+    return t;
+}
+
+// Row tiling of a streaming pass with block width K: one round of tiles.
+struct Geo {
+    int TM, n_rt;
+};
+Geo geo_for(const Ctx& c, int K, bool rebuild) {
+    const int m = (int)c.p->m;
+    const int slots = stream_occupancy(K, c.dtype, rebuild) * c.dev->cus;
+    int n_rt = n_rt_for(m, c.L.n_ct, slots < STREAM_MAX_SLOTS ? slots : STREAM_MAX_SLOTS);
+    int TM = (m + n_rt - 1) / n_rt;
+    TM = (TM + STREAM_WAVES - 1) / STREAM_WAVES * STREAM_WAVES;
+    Geo g;
+    g.TM = TM;
+    g.n_rt = (m + TM - 1) / TM;
+    return g;
+}
+
+StreamArgs stream_args(const Ctx& c, const void* D, int body, const Geo& g) {
+    StreamArgs a;
+    memset(&a, 0, sizeof(a));
+    a.D = D;
+    a.ldd = c.p->ldd;
+    a.m = (int)c.p->m;
+    a.n = (int)c.p->n;
+    a.AL = c.ws + c.L.off_AL;
+    a.BL = c.ws + c.L.off_BL;
+    a.Uf = c.ws + c.L.off_Uf;
+    a.Vf = c.ws + c.L.off_Vf;
+    a.ctrl = c.ctrl();
+    a.P1 = c.ws + c.L.off_P1;
+    a.P2 = c.ws + c.L.off_P2;
+    a.resid = c.at<double>(c.L.off_resid);
+    a.TM = g.TM;
+    a.n_ct = c.L.n_ct;
+    a.n_rt = g.n_rt;
+    const size_t row_bytes = (size_t)c.p->ldd * c.L.elt;
+    a.vec_ok = (((uintptr_t)D & 15u) == 0 && (row_bytes & 15u) == 0) ? 1 : 0;
+    a.body = body;
+    return a;
+}
+
+PanelArgs panel_args(const Ctx& c, const Geo& g = Geo{0, 1}) {
+    PanelArgs a;
+    memset(&a, 0, sizeof(a));
+    a.m = (int)c.p->m;
+    a.n = (int)c.p->n;
+    a.gU = c.L.gU;
+    a.gV = c.L.gV;
+    a.ctrl = c.ctrl();
+    a.small = c.small();
+    a.gpart = c.at<double>(c.L.off_gpart);
+    a.P1 = c.ws + c.L.off_P1;
+    a.P2 = c.ws + c.L.off_P2;
+    a.n_ct = c.L.n_ct;
+    a.n_rt = g.n_rt;
+    a.resid = c.at<double>(c.L.off_resid);
+    a.n_tiles = c.L.n_ct * g.n_rt;
+    a.Y1 = c.at<double>(c.L.off_Y1);
+    a.Y2 = c.at<double>(c.L.off_Y2);
+    a.W1 = c.at<double>(c.L.off_W1);
+    a.W2 = c.at<double>(c.L.off_W2);
+    a.Ap = c.at<double>(c.L.off_Ap);
+    a.Bp = c.at<double>(c.L.off_Bp);
+    a.Uf = c.ws + c.L.off_Uf;
+    a.Vf = c.ws + c.L.off_Vf;
+    a.AL = c.ws + c.L.off_AL;
+    a.BL = c.ws + c.L.off_BL;
+    a.host_status = c.dev->status_dev;
+    a.body = BODY_ANY;
+    return a;
+}
+
+int setup(const Ctx& c, const Ctrl& t) {
+    HIP_TRY(launch_setup(c.ctrl(), t, c.s));
+    return RPCA_OK;
+}
+
+// One loop body: stream pass, gather, complement, update (from M), basis.
+int enqueue_body(const Ctx& c, const void* D, int K, int body, double* state_U, double* state_V,
+                 double* state_sigma, bool with_hist) {
+    const bool rebuild = body != BODY_INIT;
+    const Geo g = geo_for(c, K, rebuild);
+    StreamArgs sa = stream_args(c, D, body, g);
+    RPCA_TRY(stream_launch(sa, K, c.dtype, rebuild, c.s));
+    PanelArgs pa = panel_args(c, g);
+    pa.body = body;
+    if (with_hist) {
+        pa.err_hist = c.err_hist();
+        pa.zeta_hist = c.zeta_hist();
+        pa.hist_cap = c.p->max_iter + 1;
+    }
+    HIP_TRY(launch_gather(pa, K, c.dtype, c.s));
+    HIP_TRY(launch_complement(pa, K, c.dtype, c.s));
+    PanelArgs ua = pa;
+    ua.mode = UPDATE_FROM_M;
+    if (body == BODY_INIT) {
+        ua.Unew = c.at<double>(c.L.off_Unew);
+        ua.Vnew = c.at<double>(c.L.off_Vnew);
+    } else {
+        ua.Unew = state_U;
+        ua.Vnew = state_V;
+        ua.sigma_dst = state_sigma;
+    }
+    HIP_TRY(launch_update(ua, K, c.dtype, c.s));
+    PanelArgs ba = pa;
+    ba.gated = 1;
+    HIP_TRY(launch_basis(ba, K, c.dtype, c.s));
+    return RPCA_OK;
+}
+
+// Enter the loop from factors src (stride ld_src) with singular values src_sigma:
+// rebuild factors, Trim, and orthonormal bases. Optional FP64 copies of the bases.
+int enqueue_enter(const Ctx& c, const double* srcU, const double* srcV, int64_t ld_src,
+                  const double* src_sigma, double* dstU, double* dstV, double* dst_sigma, double* outU,
+                  double* outV) {
+    const int K = c.p->r;
+    PanelArgs ua = panel_args(c);
+    ua.mode = UPDATE_ENTER;
+    ua.srcU = srcU;
+    ua.srcV = srcV;
+    ua.ld_src = ld_src;
+    ua.src_sigma = src_sigma;
+    ua.Unew = dstU;
+    ua.Vnew = dstV;
+    ua.sigma_dst = dst_sigma;
+    HIP_TRY(launch_update(ua, K, c.dtype, c.s));
+    PanelArgs ba = panel_args(c);
+    ba.gated = 0;
+    ba.outU = outU;
+    ba.outV = outV;
+    HIP_TRY(launch_basis(ba, K, c.dtype, c.s));
+    return RPCA_OK;
+}
+
+// Runs queued bodies until `finished(status)`; keeps one body queued ahead.
+template <typename Enq, typename Fin>
+int pipelined_loop(const Ctx& c, int max_bodies, Enq enqueue, Fin finished) {
+    constexpr int NEV = 4;
+    hipEvent_t ev[NEV];
+    for (int i = 0; i < NEV; ++i) HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    int rc = RPCA_OK;
+    int b = 0;
+    for (; b < max_bodies; ++b) {
+        rc = enqueue();
+        if (rc < 0) break;
+        hipError_t e = hipEventRecord(ev[b % NEV], c.s);
+        if (e != hipSuccess) { g_last_hip_error = (int)e; rc = RPCA_EHIP; break; }
+        if (b >= 1) {
+            e = hipEventSynchronize(ev[(b - 1) % NEV]);
+            if (e != hipSuccess) { g_last_hip_error = (int)e; rc = RPCA_EHIP; break; }
+            HostStatus st;
+            memcpy(&st, (const void*)c.dev->status_host, sizeof(st));
+            if (finished(st)) {
+                prof_drop_last();   // body b was queued after the stop: a no-op
+                break;
+            }
+        }
+    }
+    hipError_t e = hipStreamSynchronize(c.s);
+    if (e != hipSuccess && rc >= 0) { g_last_hip_error = (int)e; rc = RPCA_EHIP; }
+    for (int i = 0; i < NEV; ++i) (void)hipEventDestroy(ev[i]);
+    return rc;
+}
+
+int read_ctrl(const Ctx& c, Ctrl* out) {
+    HIP_TRY(hipMemcpyAsync(out, c.ctrl(), sizeof(Ctrl), hipMemcpyDeviceToHost, c.s));
+    HIP_TRY(hipStreamSynchronize(c.s));
+    return RPCA_OK;
+}
+
+// Algorithm 3 on the device; leaves the caller's state at L_0 and the
+// workspace ready for the first loop body (bases of Trim(L_0), zeta_0).
+int run_init(const Ctx& c, const void* D, rpca_state* st, Ctrl* ctrl_out) {
+    const int P = c.L.K_init;
+    Ctrl t = base_ctrl(c, STAGE_SIGMA_D, INFINITY, 0, 1.0, 0);
+    RPCA_TRY(setup(c, t));
+    PanelArgs sa = panel_args(c);
+    sa.seed = c.p->seed;
+    HIP_TRY(launch_start(sa, P, c.s));
+    PanelArgs ba = panel_args(c);
+    ba.gated = 0;
+    HIP_TRY(launch_basis(ba, P, c.dtype, c.s));
+    const int max_bodies = 2 * t.init_max_passes + 4;
+    int rc = pipelined_loop(
+        c, max_bodies,
+        [&]() { return enqueue_body(c, D, P, BODY_INIT, nullptr, nullptr, nullptr, false); },
+        [&](const HostStatus& hs) { return hs.stage >= STAGE_INIT_DONE; });
+    RPCA_TRY(rc);
+    Ctrl now;
+    RPCA_TRY(read_ctrl(c, &now));
+    if (now.stage < STAGE_INIT_DONE) return RPCA_EHIP;   // unreachable: the pass cap forces convergence
+    // L_0: the leading r columns of the converged block
+    RPCA_TRY(enqueue_enter(c, c.at<double>(c.L.off_Unew), c.at<double>(c.L.off_Vnew), P,
+                           c.small()->sigma_new, st->U, st->V, st->sigma, nullptr, nullptr));
+    *ctrl_out = now;
+    return RPCA_OK;
+}
+
+// One streaming pass plus gather at the current factors and zeta (rank r):
+// residual, err and products for this state.
+int threshold_pass(const Ctx& c, const void* D, bool rebuild) {
+    const int K = c.p->r;
+    const Geo g = geo_for(c, K, rebuild);
+    RPCA_TRY(stream_launch(stream_args(c, D, BODY_ANY, g), K, c.dtype, rebuild, c.s));
+    HIP_TRY(launch_gather(panel_args(c, g), K, c.dtype, c.s));
+    return RPCA_OK;
+}
+
+void fill_state(rpca_state* st, const Ctrl& t) {
+    st->zeta = t.zeta;
+    st->err = t.err;
+    st->k = t.k;
+    st->sigma1_pt = t.sig1_pt;
+    st->sigma_r1_pt = t.sigr1_pt;
+    st->normD = sqrt(t.normD2);
+}
+
+int check_state(const rpca_state* st) {
+    if (!st || !st->U || !st->V || !st->sigma) return RPCA_EINVAL;
+    return RPCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rpca_version(void) { return 100; }
+
+int rpca_profile_enable(int on) {
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    if (!on) RPCA_TRY(prof_collect_locked());
+    g_prof.on = on != 0;
+    return RPCA_OK;
+}
+
+int rpca_profile_read(double* stream_ms, int64_t* stream_launches) {
+    if (!stream_ms || !stream_launches) return RPCA_EINVAL;
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    RPCA_TRY(prof_collect_locked());
+    *stream_ms = g_prof.ms;
+    *stream_launches = g_prof.launches;
+    g_prof.ms = 0.0;
+    g_prof.launches = 0;
+    return RPCA_OK;
+}
+
+int rpca_last_hip_error(void) { return g_last_hip_error; }
+
+const char* rpca_strerror(int status) {
+    switch (status) {
+        case RPCA_OK: return "success";
+        case RPCA_MAXITER: return "iteration cap reached before err < tol";
+        case RPCA_EINVAL: return "invalid argument";
+        case RPCA_EWORKSPACE: return "workspace missing, misaligned or too small";
+        case RPCA_EHIP: return "HIP runtime error";
+        case RPCA_ENODEV: return "current device is not a gfx950 GPU";
+        default: return "unknown status";
+    }
+}
+
+int rpca_workspace_size(const rpca_params* p, size_t* bytes) {
+    RPCA_TRY(validate(p));
+    if (!bytes) return RPCA_EINVAL;
+    *bytes = make_layout(p).total;
+    return RPCA_OK;
+}
+
+int rpca_init(const void* D, const rpca_params* p, rpca_state* st, void* ws, size_t ws_bytes, void* stream) {
+    if (!D) return RPCA_EINVAL;
+    RPCA_TRY(check_state(st));
+    Ctx c;
+    RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
+    Ctrl ic;
+    RPCA_TRY(run_init(c, D, st, &ic));
+    // err_0 from one threshold pass: S_0 = T_zeta_0(D - L_0)
+    RPCA_TRY(threshold_pass(c, D, true));
+    Ctrl t;
+    RPCA_TRY(read_ctrl(c, &t));
+    fill_state(st, t);
+    st->init_passes = ic.total_passes;
+    return RPCA_OK;
+}
+
+int rpca_solve(const void* D, const rpca_params* p, rpca_state* st, double* err_hist, double* zeta_hist,
+               int32_t hist_cap, void* ws, size_t ws_bytes, void* stream) {
+    if (!D || hist_cap < 0) return RPCA_EINVAL;
+    RPCA_TRY(check_state(st));
+    Ctx c;
+    RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
+    Ctrl ic;
+    RPCA_TRY(run_init(c, D, st, &ic));
+    // switch the control block to the loop: stopping rule on, k = 0
+    Ctrl t;
+    RPCA_TRY(read_ctrl(c, &t));
+    t.want_stop = 1;
+    t.k = 0;
+    t.active = 1;
+    t.done = 0;
+    RPCA_TRY(setup(c, t));
+    int rc = pipelined_loop(
+        c, p->max_iter + 3,
+        [&]() { return enqueue_body(c, D, p->r, BODY_MAIN, st->U, st->V, st->sigma, true); },
+        [&](const HostStatus& hs) { return hs.done != 0; });
+    RPCA_TRY(rc);
+    Ctrl fin;
+    RPCA_TRY(read_ctrl(c, &fin));
+    fill_state(st, fin);
+    st->init_passes = ic.total_passes;
+    const int n = fin.k + 1;
+    const int cnt = n < hist_cap ? n : hist_cap;
+    if (cnt > 0 && err_hist) HIP_TRY(hipMemcpyAsync(err_hist, c.err_hist(), sizeof(double) * cnt, hipMemcpyDeviceToHost, c.s));
+    if (cnt > 0 && zeta_hist) HIP_TRY(hipMemcpyAsync(zeta_hist, c.zeta_hist(), sizeof(double) * cnt, hipMemcpyDeviceToHost, c.s));
+    HIP_TRY(hipStreamSynchronize(c.s));
+    return fin.stopped_by_tol ? RPCA_OK : RPCA_MAXITER;
+}
+
+int rpca_trim(const rpca_params* p, const rpca_state* st, double* U_tilde, double* V_tilde, void* ws,
+              size_t ws_bytes, void* stream) {
+    RPCA_TRY(check_state(st));
+    if (!U_tilde || !V_tilde) return RPCA_EINVAL;
+    Ctx c;
+    RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
+    RPCA_TRY(setup(c, base_ctrl(c, STAGE_MAIN, st->zeta, st->k, 1.0, 0)));
+    RPCA_TRY(enqueue_enter(c, st->U, st->V, p->r, st->sigma, nullptr, nullptr, nullptr, U_tilde, V_tilde));
+    HIP_TRY(hipStreamSynchronize(c.s));
+    return RPCA_OK;
+}
+
+namespace {
+// ||D||_F^2 by one pass with zeta = +inf (every entry counts in the residual).
+int compute_normD2(const Ctx& c, const void* D, double* out) {
+    RPCA_TRY(setup(c, base_ctrl(c, STAGE_SIGMA_D, INFINITY, 0, 1.0, 0)));
+    RPCA_TRY(threshold_pass(c, D, false));
+    Ctrl t;
+    RPCA_TRY(read_ctrl(c, &t));
+    *out = t.normD2;
+    return RPCA_OK;
+}
+}  // namespace
+
+int rpca_step(const void* D, const rpca_params* p, rpca_state* st, void* ws, size_t ws_bytes, void* stream) {
+    if (!D) return RPCA_EINVAL;
+    RPCA_TRY(check_state(st));
+    if (!is_fin(st->zeta) || st->k < 0) return RPCA_EINVAL;
+    Ctx c;
+    RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
+    double nd2 = st->normD > 0 ? st->normD * st->normD : 0.0;
+    if (!(nd2 > 0)) RPCA_TRY(compute_normD2(c, D, &nd2));
+    RPCA_TRY(setup(c, base_ctrl(c, STAGE_MAIN, st->zeta, st->k, nd2, 0)));
+    const int K = p->r;
+    // Trim(L_k) and its orthonormal bases
+    RPCA_TRY(enqueue_enter(c, st->U, st->V, K, st->sigma, nullptr, nullptr, nullptr, nullptr, nullptr));
+    // products with Z_k, the 2r x 2r update, zeta_{k+1}; L_{k+1} overwrites the state
+    RPCA_TRY(enqueue_body(c, D, K, BODY_ANY, st->U, st->V, st->sigma, false));
+    // err_{k+1}: threshold pass at (L_{k+1}, zeta_{k+1})
+    RPCA_TRY(threshold_pass(c, D, true));
+    Ctrl t;
+    RPCA_TRY(read_ctrl(c, &t));
+    fill_state(st, t);
+    return RPCA_OK;
+}
+
+int rpca_materialize(const void* D, const rpca_params* p, const rpca_state* st, void* L_out, int64_t ldl,
+                     void* S_out, int64_t lds, void* ws, size_t ws_bytes, void* stream) {
+    if (!D) return RPCA_EINVAL;
+    RPCA_TRY(check_state(st));
+    if ((L_out && ldl < p->n) || (S_out && lds < p->n)) return RPCA_EINVAL;
+    Ctx c;
+    RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
+    RPCA_TRY(setup(c, base_ctrl(c, STAGE_MAIN, st->zeta, st->k, 1.0, 0)));
+    const int K = p->r;
+    HIP_TRY(launch_convert(st->U, c.ws + c.L.off_AL, p->m * K, st->sigma, K, c.dtype, c.s));
+    HIP_TRY(launch_convert(st->V, c.ws + c.L.off_BL, p->n * K, nullptr, K, c.dtype, c.s));
+    MaterializeArgs a;
+    a.D = D;
+    a.ldd = p->ldd;
+    a.m = (int)p->m;
+    a.n = (int)p->n;
+    a.AL = c.ws + c.L.off_AL;
+    a.BL = c.ws + c.L.off_BL;
+    a.ctrl = c.ctrl();
+    a.L_out = L_out;
+    a.ldl = ldl;
+    a.S_out = S_out;
+    a.lds = lds;
+    if (L_out || S_out) HIP_TRY(launch_materialize(a, K, c.dtype, c.s));
+    HIP_TRY(hipStreamSynchronize(c.s));
+    return RPCA_OK;
+}
+
+int rpca_tangent_products(const void* D, const rpca_params* p, const double* A_L, const double* B_L,
+                          double zeta, const double* U_t, const double* V_t, double* Y1, double* Y2,
+                          double* resid2, void* ws, size_t ws_bytes, void* stream) {
+    if (!D || !A_L || !B_L || !U_t || !V_t || !Y1 || !Y2 || !resid2 || isnan(zeta)) return RPCA_EINVAL;
+    Ctx c;
+    RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
+    const int K = p->r;
+    RPCA_TRY(setup(c, base_ctrl(c, STAGE_MAIN, zeta, 0, 1.0, 0)));
+    HIP_TRY(launch_convert(A_L, c.ws + c.L.off_AL, p->m * K, nullptr, K, c.dtype, c.s));
+    HIP_TRY(launch_convert(B_L, c.ws + c.L.off_BL, p->n * K, nullptr, K, c.dtype, c.s));
+    HIP_TRY(launch_convert(U_t, c.ws + c.L.off_Uf, p->m * K, nullptr, K, c.dtype, c.s));
+    HIP_TRY(launch_convert(V_t, c.ws + c.L.off_Vf, p->n * K, nullptr, K, c.dtype, c.s));
+    const Geo g = geo_for(c, K, true);
+    RPCA_TRY(stream_launch(stream_args(c, D, BODY_ANY, g), K, c.dtype, true, c.s));
+    PanelArgs pa = panel_args(c, g);
+    pa.Y1 = Y1;
+    pa.Y2 = Y2;
+    HIP_TRY(launch_gather(pa, K, c.dtype, c.s));
+    Ctrl t;
+    RPCA_TRY(read_ctrl(c, &t));
+    *resid2 = t.resid2;
+    return RPCA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// Shared definitions of librpca: workspace control block, small FP64 matrix
+// area, launch constants and device helpers used by several kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rpca {
+
+constexpr int KMAX = 16;          // largest rank / init block handled by the kernels
+constexpr int WAVE = 64;          // CDNA wavefront width
+constexpr int STREAM_THREADS = 256;
+constexpr int STREAM_WAVES = STREAM_THREADS / WAVE;
+constexpr int STREAM_CPL = 4;     // consecutive columns owned by one lane
+constexpr int STREAM_TN = WAVE * STREAM_CPL;   // columns per stream tile
+constexpr int PANEL_THREADS = 256;
+constexpr int GATHER_SPLIT = 4;   // threads sharing one row in the gather kernel
+
+// Stages of the device-side state machine (Ctrl::stage).
+enum Stage : int {
+    STAGE_SIGMA_D = 0,   // init: subspace iteration on D for sigma_1(D)
+    STAGE_INIT_Z = 1,    // init: subspace iteration on D - T_{zeta_-1}(D)
+    STAGE_INIT_DONE = 2, // init converged; host switches to rank-r kernels
+    STAGE_MAIN = 3,      // AccAltProj loop
+};
+
+// Which loop a kernel launch belongs to (gating of speculatively queued bodies).
+enum Body : int {
+    BODY_INIT = 0,   // runs only while the initial subspace iteration is in progress
+    BODY_MAIN = 1,   // runs only while the AccAltProj loop has not stopped
+    BODY_ANY = 2,    // always runs (single steps, tests)
+};
+
+// Counter slots for the last-workgroup-finishes pattern.
+enum CounterSlot : int {
+    CNT_GATHER = 0, CNT_COMPLEMENT = 1, CNT_UPDATE = 2, CNT_BASIS = 3, CNT_START = 4,
+    CNT_COUNT = 8,
+};
+
+// Host-visible status written by the gather kernel into mapped pinned memory.
+struct HostStatus {
+    int32_t seq;         // number of gather kernels completed
+    int32_t done;        // loop finished
+    int32_t stage;
+    int32_t k;
+    double err;
+    double zeta;
+};
+
+// Control block at the start of the workspace (device memory).
+struct Ctrl {
+    uint32_t cnt[CNT_COUNT];
+    int32_t done;        // main loop finished (err < tol or k == max_iter)
+    int32_t stage;
+    int32_t k;           // index of the current state (L_k, S_k)
+    int32_t passes;      // passes over D in the current init stage
+    int32_t total_passes;
+    int32_t max_iter;
+    int32_t keep;        // singular triplets kept from M (p in init, r in main)
+    int32_t r;
+    int32_t p;
+    int32_t init_max_passes;
+    int32_t trim;        // 1: apply Algorithm 2 in the update kernel
+    int32_t want_stop;   // 1: gather kernel applies the stopping rule
+    int32_t seq;
+    int32_t stopped_by_tol;
+    int32_t active;      // 1 while the current loop body is live (set by the gather kernel)
+    int32_t jacobi_sweeps;   // sweeps of the last 2K x 2K SVD (diagnostic)
+    double zeta;         // threshold used by the next stream pass
+    double err;          // err of the current state
+    double normD2;       // ||D||_F^2
+    double beta, beta_init, gamma, mu, tol;
+    double res_prev;     // init convergence tracking
+    double sigma1_D;
+    double sig1_pt, sigr1_pt;   // sigma_1 and sigma_{r+1} of the last P_T(D - S_k)
+    double tol_res_a, tol_res_b;
+    double resid2;       // last residual sum (sum over |x| <= zeta of x^2)
+};
+
+// Small FP64 matrices shared between kernels (all K x K, row-major, ld = KMAX).
+struct Small {
+    double RUinv[KMAX * KMAX];   // R_U^{-1}: Gram(U_f) = R_U^T R_U
+    double RVinv[KMAX * KMAX];
+    double Cstar[KMAX * KMAX];   // C* = R_U^{-T} U_f^T Y1 R_V^{-1}
+    double X1[KMAX * KMAX];      // U_new = U* X1 + W1 X2
+    double X2[KMAX * KMAX];
+    double Z1[KMAX * KMAX];      // V_new = V* Z1 + W2 Z2
+    double Z2[KMAX * KMAX];
+    double RAinv[KMAX * KMAX];   // Gram(A) = R_A^T R_A (Trim output)
+    double RBinv[KMAX * KMAX];
+    double sigma_new[KMAX];
+    double sigma_M[2 * KMAX];
+};
+
+__host__ __device__ constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- device --
+
+template <typename T> struct AccOf;
+template <> struct AccOf<float> { using type = float; };
+template <> struct AccOf<double> { using type = double; };
+
+// Sum of one double over the 256 threads of a workgroup (result valid in all threads).
+__device__ inline double block_sum_256(double v, double* red /* >= 4 doubles shared */) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    const int w = threadIdx.x / WAVE;
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[w] = v;
+    __syncthreads();
+    double s = red[0] + red[1] + red[2] + red[3];
+    return s;
+}
+
+// Whether a streaming pass / gather launch of the given body executes.
+__device__ inline bool body_runs(const Ctrl* c, int body) {
+    if (body == BODY_INIT) return c->stage == STAGE_SIGMA_D || c->stage == STAGE_INIT_Z;
+    if (body == BODY_MAIN) return c->done == 0;
+    return true;
+}
+
+// Signals completion of this workgroup's partial results; returns true in the
+// single workgroup that finished last. Partials written before the call are
+// visible to that workgroup afterwards. The counter is reset by the caller.
+__device__ inline bool last_block_arrives(uint32_t* counter, int* flag_smem) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t prev = atomicAdd(counter, 1u);
+        *flag_smem = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    const bool last = *flag_smem != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+}  // namespace rpca

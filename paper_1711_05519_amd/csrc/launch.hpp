@@ -1,0 +1,96 @@
+// Host-side launchers of the librpca kernels (defined next to the kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace rpca {
+
+// Arguments of the streaming pass over D (see stream.hip).
+struct StreamArgs {
+    const void* D;        // m x n, row stride ldd (T)
+    int64_t ldd;
+    int32_t m, n;
+    const void* AL;       // m x K (T): L = AL BL^T ; unused without rebuild
+    const void* BL;       // n x K (T)
+    const void* Uf;       // m x K (T): basis for Y2 = Z^T Uf
+    const void* Vf;       // n x K (T): basis for Y1 = Z Vf
+    const Ctrl* ctrl;     // zeta, done
+    void* P1;             // [n_ct][m][K] partials of Y1 (acc type)
+    void* P2;             // [n_rt][n][K] partials of Y2
+    double* resid;        // [n_ct * n_rt] partial residual sums
+    int32_t TM;           // rows per tile
+    int32_t n_ct, n_rt;
+    int32_t vec_ok;       // 1 if D rows are 16-byte aligned (vector loads allowed)
+    int32_t body;         // Body: gating of the launch
+};
+
+// Scalar geometry of the streaming pass (kernel argument; pointers are passed
+// separately so the compiler can treat them as non-aliasing).
+struct StreamGeom {
+    int64_t ldd;
+    int32_t m, n, TM, n_ct, n_rt, vec_ok, body;
+};
+
+struct MaterializeArgs {
+    const void* D;
+    int64_t ldd;
+    int32_t m, n;
+    const void* AL;
+    const void* BL;
+    const Ctrl* ctrl;
+    void* L_out; int64_t ldl;
+    void* S_out; int64_t lds;
+};
+
+// Panel-kernel arguments (one struct for all of them; unused fields ignored).
+struct PanelArgs {
+    int32_t m, n;
+    int32_t gU, gV;           // workgroups on the U side (m rows) and V side (n rows)
+    Ctrl* ctrl;
+    Small* small;
+    double* gpart;            // per-workgroup partial K x K blocks [gU + gV][KMAX*KMAX]
+    // stream partials
+    const void* P1; const void* P2; int32_t n_ct, n_rt;
+    const double* resid; int32_t n_tiles;
+    // FP64 panels
+    double* Y1; double* Y2;   // m x K, n x K
+    double* W1; double* W2;
+    double* Ap; double* Bp;   // trimmed factors / blocks to orthonormalise
+    double* Unew; double* Vnew;  // destinations of the updated factors (stride K)
+    double* sigma_dst;        // destination of sigma_new (nullable)
+    // T-typed panels
+    void* Uf; void* Vf;       // bases used by the stream pass
+    void* AL; void* BL;       // rebuild factors
+    // enter mode sources
+    const double* srcU; const double* srcV; int64_t ld_src; const double* src_sigma;
+    // optional FP64 outputs of the basis kernel
+    double* outU; double* outV;
+    // histories and host status
+    double* err_hist; double* zeta_hist; int32_t hist_cap;
+    HostStatus* host_status;
+    uint64_t seed;
+    int32_t mode;             // kernel-specific
+    int32_t body;             // Body of the gather kernel
+    int32_t gated;            // basis kernel: skip when the body is not active
+};
+
+enum UpdateMode : int { UPDATE_FROM_M = 0, UPDATE_ENTER = 1 };
+
+// dtype: 0 = double, 1 = float
+// Workgroups of the streaming pass resident per CU (from the HIP occupancy API).
+int stream_occupancy(int K, int dtype, bool rebuild);
+hipError_t launch_stream(const StreamArgs& a, int K, int dtype, bool rebuild, hipStream_t s);
+hipError_t launch_materialize(const MaterializeArgs& a, int K, int dtype, hipStream_t s);
+hipError_t launch_gather(const PanelArgs& a, int K, int dtype, hipStream_t s);
+hipError_t launch_complement(const PanelArgs& a, int K, int dtype, hipStream_t s);
+hipError_t launch_update(const PanelArgs& a, int K, int dtype, hipStream_t s);
+hipError_t launch_basis(const PanelArgs& a, int K, int dtype, hipStream_t s);
+hipError_t launch_start(const PanelArgs& a, int K, hipStream_t s);
+hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, hipStream_t s);
+hipError_t launch_convert(const double* src, void* dst, int64_t count, const double* scale, int K,
+                          int dtype, hipStream_t s);
+
+}  // namespace rpca

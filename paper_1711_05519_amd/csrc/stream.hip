@@ -1,0 +1,440 @@
+// The streaming pass over D: the only kernels of an iteration that touch the
+// m x n data. One read of D computes, for the current iterate L = AL BL^T and
+// threshold zeta (Section 2.1 and Algorithm 1):
+//   x = D - L,  S = T_zeta(x)  (never stored),  Z = D - S,
+//   resid = sum over |x| <= zeta of x^2          (numerator of err^2, Section 3)
+//   Y1 = Z Vf,  Y2 = Z^T Uf                      (the two n x n by n x r products
+//                                                  of the fast H_r(P_T(.)) update)
+// so that the threshold of iteration k and the tangent products of iteration
+// k+1 share one pass. L is rebuilt tile by tile in registers and never written.
+//
+// Layout: a workgroup of 4 waves owns a tile of TM rows x 256 columns. Each lane
+// owns 4 consecutive columns (one 16-byte load per row for FP32) and keeps the
+// matching rows of BL and Vf in registers; the 4 waves walk interleaved rows.
+// Row data (AL, Uf) are wave-uniform and come through scalar loads. Y2 then
+// accumulates per lane with no communication; the per-row sums of Y1 are
+// reduced across the 64 lanes in batches with a reduce-scatter built from
+// v_permlane32_swap, v_permlane16_swap and DPP moves, which leaves one finished
+// sum per lane. Tile partials go to P1/P2 and are summed in FP64 by the gather
+// kernel in a fixed order, so results are bitwise reproducible.
+#include "launch.hpp"
+
+namespace rpca {
+namespace {
+
+template <typename T> __device__ inline T zero() { return T(0); }
+
+// ---- cross-lane moves on 32/64-bit values ----------------------------------
+
+__device__ inline void swap32(float& a, float& b) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+__device__ inline void swap16(float& a, float& b) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+__device__ inline void swap32(double& a, double& b) {
+    uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)ua, (uint32_t)ub, false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
+    a = __longlong_as_double((int64_t)(((uint64_t)hi[0] << 32) | lo[0]));
+    b = __longlong_as_double((int64_t)(((uint64_t)hi[1] << 32) | lo[1]));
+}
+__device__ inline void swap16(double& a, double& b) {
+    uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)ua, (uint32_t)ub, false, false);
+    auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
+    a = __longlong_as_double((int64_t)(((uint64_t)hi[0] << 32) | lo[0]));
+    b = __longlong_as_double((int64_t)(((uint64_t)hi[1] << 32) | lo[1]));
+}
+
+template <int CTRL> __device__ inline float dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL> __device__ inline double dpp(double x) {
+    int64_t u = __double_as_longlong(x);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// DPP controls: row_ror:8 pairs lane l with l^8; row_half_mirror with l^7;
+// quad_perm[2,3,0,1] with l^2; quad_perm[1,0,3,2] with l^1.
+constexpr int DPP_ROR8 = 0x128;
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_QP_2301 = 0x4E;
+constexpr int DPP_QP_1032 = 0xB1;
+
+// One level of the reduce-scatter: N values per lane -> ceil(N/2) values per
+// lane. Lanes whose level bit is clear keep family 2k, the others family 2k+1.
+template <int N, typename T>
+__device__ inline void level_swap32(T (&x)[N], T (&y)[(N + 1) / 2]) {
+#pragma unroll
+    for (int k = 0; k < N / 2; ++k) {
+        T a = x[2 * k], b = x[2 * k + 1];
+        swap32(a, b);
+        y[k] = a + b;
+    }
+    if constexpr (N & 1) {
+        T a = x[N - 1], b = zero<T>();
+        swap32(a, b);
+        y[N / 2] = a + b;
+    }
+}
+template <int N, typename T>
+__device__ inline void level_swap16(T (&x)[N], T (&y)[(N + 1) / 2]) {
+#pragma unroll
+    for (int k = 0; k < N / 2; ++k) {
+        T a = x[2 * k], b = x[2 * k + 1];
+        swap16(a, b);
+        y[k] = a + b;
+    }
+    if constexpr (N & 1) {
+        T a = x[N - 1], b = zero<T>();
+        swap16(a, b);
+        y[N / 2] = a + b;
+    }
+}
+template <int CTRL, int BIT, int N, typename T>
+__device__ inline void level_dpp(T (&x)[N], T (&y)[(N + 1) / 2], int lane) {
+    const bool hi = (lane >> BIT) & 1;
+#pragma unroll
+    for (int k = 0; k < N / 2; ++k) {
+        T a = x[2 * k], b = x[2 * k + 1];
+        T keep = hi ? b : a;
+        T send = hi ? a : b;
+        y[k] = keep + dpp<CTRL>(send);
+    }
+    if constexpr (N & 1) y[N / 2] = x[N - 1] + dpp<CTRL>(x[N - 1]);
+}
+
+// Sums each of the V values over the 64 lanes. On return lane l holds the
+// total of value index bitrev6(l) (valid when that index is < V).
+template <int V, typename T>
+__device__ inline T reduce_scatter64(T (&x)[V], int lane) {
+    static_assert(V >= 1 && V <= 64, "reduce_scatter64 handles at most 64 values");
+    constexpr int V1 = (V + 1) / 2, V2 = (V1 + 1) / 2, V3 = (V2 + 1) / 2, V4 = (V3 + 1) / 2,
+                  V5 = (V4 + 1) / 2, V6 = (V5 + 1) / 2;
+    static_assert(V6 == 1, "levels");
+    T y1[V1], y2[V2], y3[V3], y4[V4], y5[V5], y6[V6];
+    level_swap32<V>(x, y1);
+    level_swap16<V1>(y1, y2);
+    level_dpp<DPP_ROR8, 3, V2>(y2, y3, lane);
+    level_dpp<DPP_HALF_MIRROR, 2, V3>(y3, y4, lane);
+    level_dpp<DPP_QP_2301, 1, V4>(y4, y5, lane);
+    level_dpp<DPP_QP_1032, 0, V5>(y5, y6, lane);
+    return y6[0];
+}
+
+__device__ inline int bitrev6(int l) {
+    return ((l & 1) << 5) | ((l & 2) << 3) | ((l & 4) << 1) | ((l & 8) >> 1) | ((l & 16) >> 3) |
+           ((l & 32) >> 5);
+}
+
+// ---- loads of 4 consecutive elements -----------------------------------------
+
+__device__ inline void load4(const float* __restrict__ p, int nvalid, bool vec, float (&d)[4]) {
+    if (nvalid == 4 && vec) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) d[s] = s < nvalid ? p[s] : 0.f;
+    }
+}
+__device__ inline void load4(const double* __restrict__ p, int nvalid, bool vec, double (&d)[4]) {
+    if (nvalid == 4 && vec) {
+        const double2 v0 = reinterpret_cast<const double2*>(p)[0];
+        const double2 v1 = reinterpret_cast<const double2*>(p)[1];
+        d[0] = v0.x; d[1] = v0.y; d[2] = v1.x; d[3] = v1.y;
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) d[s] = s < nvalid ? p[s] : 0.0;
+    }
+}
+
+template <typename T, int K> struct StreamCfg {
+    // Rows per batch per wave. The batch's wave-uniform row data (2K values of
+    // AL and Uf per row) live in scalar registers; about 60 SGPRs of them fit
+    // without spilling. The per-element cost of the reduce-scatter depends on
+    // NB * K only weakly, so smaller batches cost little.
+    static constexpr int WORDS = (int)(sizeof(T) / 4);
+    static constexpr int NB0 = 32 / (K * WORDS);
+    static constexpr int NB = NB0 < 1 ? 1 : (NB0 > 8 ? 8 : NB0);
+};
+
+// Loads rows i0, i0 + 4, ... of the wave's 4 columns.
+template <typename T, int K, bool FULL, bool CHECK>
+__device__ __forceinline__ void load_batch(const T* __restrict__ D, int64_t ldd, int i0, int i_hi, int jb,
+                                           int nvalid, T (&d)[StreamCfg<T, K>::NB][STREAM_CPL]) {
+    constexpr int NB = StreamCfg<T, K>::NB;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int i = i0 + STREAM_WAVES * b;
+        if (!CHECK || i < i_hi) {
+            load4(D + (size_t)i * ldd + jb, FULL ? STREAM_CPL : nvalid, FULL, d[b]);
+        } else {
+#pragma unroll
+            for (int s = 0; s < STREAM_CPL; ++s) d[b][s] = T(0);
+        }
+    }
+}
+
+// Threshold, residual and both product contributions of one loaded batch.
+template <typename T, int K, bool REBUILD, bool CHECK>
+__device__ __forceinline__ void compute_batch(
+    const T (&d)[StreamCfg<T, K>::NB][STREAM_CPL], const T* __restrict__ AL, const T* __restrict__ Uf,
+    int i0, int i_hi, T zeta, const T (&bl)[STREAM_CPL][K], const T (&vt)[STREAM_CPL][K],
+    T (&y2)[STREAM_CPL][K], double& res, typename AccOf<T>::type* __restrict__ P1t, int lane) {
+    using Acc = typename AccOf<T>::type;
+    constexpr int NB = StreamCfg<T, K>::NB;
+    T p[NB * K];
+    T rs = T(0);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int i = i0 + STREAM_WAVES * b;
+#pragma unroll
+        for (int t = 0; t < K; ++t) p[b * K + t] = T(0);
+        if (!CHECK || i < i_hi) {
+            T al[K], ut[K];
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                al[t] = REBUILD ? AL[(size_t)i * K + t] : T(0);
+                ut[t] = Uf[(size_t)i * K + t];
+            }
+#pragma unroll
+            for (int s = 0; s < STREAM_CPL; ++s) {
+                const T dv = d[b][s];
+                T x = dv;
+                if constexpr (REBUILD) {
+#pragma unroll
+                    for (int t = 0; t < K; ++t) x = fma(-al[t], bl[s][t], x);
+                }
+                const bool big = fabs(x) > zeta;   // S_ij = x  (T_zeta keeps |x| > zeta)
+                const T e = big ? T(0) : x;        // entry of D - L - S
+                rs = fma(e, e, rs);
+                const T z = big ? dv - x : dv;     // Z = D - S
+#pragma unroll
+                for (int t = 0; t < K; ++t) {
+                    y2[s][t] = fma(z, ut[t], y2[s][t]);
+                    p[b * K + t] = fma(z, vt[s][t], p[b * K + t]);
+                }
+            }
+        }
+    }
+    res += static_cast<double>(rs);
+    const T tot = reduce_scatter64<NB * K>(p, lane);
+    const int q = bitrev6(lane);
+    if (q < NB * K) {
+        const int b = q / K, t = q - (q / K) * K;
+        const int i = i0 + STREAM_WAVES * b;
+        if (i < i_hi) P1t[(size_t)i * K + t] = static_cast<Acc>(tot);
+    }
+}
+
+// All rows of the tile for one wave. Full batches are software-pipelined: the
+// loads of batch j+1 are issued before batch j is computed.
+template <typename T, int K, bool REBUILD, bool FULL>
+__device__ __forceinline__ void stream_rows(
+    const T* __restrict__ D, int64_t ldd, const T* __restrict__ AL, const T* __restrict__ Uf,
+    int i_first, int i_hi, int jb, int nvalid, T zeta, const T (&bl)[STREAM_CPL][K],
+    const T (&vt)[STREAM_CPL][K], T (&y2)[STREAM_CPL][K], double& res,
+    typename AccOf<T>::type* __restrict__ P1t, int lane) {
+    constexpr int NB = StreamCfg<T, K>::NB;
+    constexpr int STEP = STREAM_WAVES * NB;
+    int i0 = i_first;
+    if constexpr (FULL) {
+        if (i0 + STREAM_WAVES * (NB - 1) < i_hi) {
+            T cur[NB][STREAM_CPL], nxt[NB][STREAM_CPL];
+            load_batch<T, K, true, false>(D, ldd, i0, i_hi, jb, nvalid, nxt);
+            for (;;) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int s = 0; s < STREAM_CPL; ++s) cur[b][s] = nxt[b][s];
+                const int i1 = i0 + STEP;
+                const bool more = i1 + STREAM_WAVES * (NB - 1) < i_hi;
+                if (more) load_batch<T, K, true, false>(D, ldd, i1, i_hi, jb, nvalid, nxt);
+                compute_batch<T, K, REBUILD, false>(cur, AL, Uf, i0, i_hi, zeta, bl, vt, y2, res, P1t, lane);
+                i0 = i1;
+                if (!more) break;
+            }
+        }
+    }
+    for (; i0 < i_hi; i0 += STEP) {
+        T cur[NB][STREAM_CPL];
+        load_batch<T, K, FULL, true>(D, ldd, i0, i_hi, jb, nvalid, cur);
+        compute_batch<T, K, REBUILD, true>(cur, AL, Uf, i0, i_hi, zeta, bl, vt, y2, res, P1t, lane);
+    }
+}
+
+template <typename T, int K, bool REBUILD>
+__global__ __launch_bounds__(STREAM_THREADS) void k_stream(
+    const T* __restrict__ D, const T* __restrict__ AL, const T* __restrict__ BL, const T* __restrict__ Uf,
+    const T* __restrict__ Vf, typename AccOf<T>::type* __restrict__ P1, typename AccOf<T>::type* __restrict__ P2,
+    double* __restrict__ resid, const Ctrl* __restrict__ ctrl, StreamGeom g) {
+    using Acc = typename AccOf<T>::type;
+    if (!body_runs(ctrl, g.body)) return;
+    const T zeta = static_cast<T>(ctrl->zeta);
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int ct = blockIdx.x % g.n_ct;
+    const int rt = blockIdx.x / g.n_ct;
+    const int jb = ct * STREAM_TN + lane * STREAM_CPL;
+    const int nvalid = min(max(g.n - jb, 0), STREAM_CPL);
+
+    T bl[STREAM_CPL][K], vt[STREAM_CPL][K], y2[STREAM_CPL][K];
+#pragma unroll
+    for (int s = 0; s < STREAM_CPL; ++s) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const bool ok = s < nvalid;
+            bl[s][t] = (REBUILD && ok) ? BL[(size_t)(jb + s) * K + t] : T(0);
+            vt[s][t] = ok ? Vf[(size_t)(jb + s) * K + t] : T(0);
+            y2[s][t] = T(0);
+        }
+    }
+
+    const int i_lo = rt * g.TM;
+    const int i_hi = min(g.m, i_lo + g.TM);
+    double res = 0.0;
+    Acc* P1t = P1 + (size_t)ct * g.m * K;
+    const bool full = g.vec_ok && (ct + 1) * STREAM_TN <= g.n;   // uniform per workgroup
+    if (full)
+        stream_rows<T, K, REBUILD, true>(D, g.ldd, AL, Uf, i_lo + wave, i_hi, jb, nvalid, zeta, bl, vt, y2, res,
+                                         P1t, lane);
+    else
+        stream_rows<T, K, REBUILD, false>(D, g.ldd, AL, Uf, i_lo + wave, i_hi, jb, nvalid, zeta, bl, vt, y2, res,
+                                          P1t, lane);
+
+    // Y2 partial: sum the four waves' column partials through LDS.
+    __shared__ Acc sm[STREAM_TN * K];
+    __shared__ double red[STREAM_WAVES];
+    for (int w = 0; w < STREAM_WAVES; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int s = 0; s < STREAM_CPL; ++s)
+#pragma unroll
+                for (int t = 0; t < K; ++t) {
+                    const int idx = (lane * STREAM_CPL + s) * K + t;
+                    sm[idx] = (w == 0) ? static_cast<Acc>(y2[s][t]) : sm[idx] + static_cast<Acc>(y2[s][t]);
+                }
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < STREAM_TN * K; idx += STREAM_THREADS) {
+        const int col = ct * STREAM_TN + idx / K;
+        if (col < g.n) P2[((size_t)rt * g.n + col) * K + (idx % K)] = sm[idx];
+    }
+    const double rtot = block_sum_256(res, red);
+    if (threadIdx.x == 0) resid[blockIdx.x] = rtot;
+}
+
+// Dense L = AL BL^T and S = T_zeta(D - L) (outputs of Algorithm 1).
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_materialize(MaterializeArgs a) {
+    const T* __restrict__ D = static_cast<const T*>(a.D);
+    const T* __restrict__ AL = static_cast<const T*>(a.AL);
+    const T* __restrict__ BL = static_cast<const T*>(a.BL);
+    T* Lo = static_cast<T*>(a.L_out);
+    T* So = static_cast<T*>(a.S_out);
+    const T zeta = static_cast<T>(a.ctrl->zeta);
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= a.n) return;
+    T b[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) b[t] = BL[(size_t)j * K + t];
+    for (int i = blockIdx.y; i < a.m; i += gridDim.y) {
+        T l = T(0);
+#pragma unroll
+        for (int t = 0; t < K; ++t) l = fma(AL[(size_t)i * K + t], b[t], l);
+        const T x = D[(size_t)i * a.ldd + j] - l;
+        if (Lo) Lo[(size_t)i * a.ldl + j] = l;
+        if (So) So[(size_t)i * a.lds + j] = fabs(x) > zeta ? x : T(0);
+    }
+}
+
+template <typename T, bool REBUILD>
+hipError_t stream_dispatch(const StreamArgs& a, int K, hipStream_t s) {
+    using Acc = typename AccOf<T>::type;
+    const dim3 grid((unsigned)(a.n_ct * a.n_rt)), block(STREAM_THREADS);
+    StreamGeom geom;
+    geom.ldd = a.ldd;
+    geom.m = a.m;
+    geom.n = a.n;
+    geom.TM = a.TM;
+    geom.n_ct = a.n_ct;
+    geom.n_rt = a.n_rt;
+    geom.vec_ok = a.vec_ok;
+    geom.body = a.body;
+    switch (K) {
+#define RPCA_CASE(KK)                                                                                      \
+    case KK:                                                                                               \
+        hipLaunchKernelGGL((k_stream<T, KK, REBUILD>), grid, block, 0, s, static_cast<const T*>(a.D),      \
+                           static_cast<const T*>(a.AL), static_cast<const T*>(a.BL),                       \
+                           static_cast<const T*>(a.Uf), static_cast<const T*>(a.Vf), static_cast<Acc*>(a.P1), \
+                           static_cast<Acc*>(a.P2), a.resid, a.ctrl, geom);                                \
+        break;
+        RPCA_CASE(1) RPCA_CASE(2) RPCA_CASE(3) RPCA_CASE(4) RPCA_CASE(5) RPCA_CASE(6)
+        RPCA_CASE(7) RPCA_CASE(8) RPCA_CASE(9) RPCA_CASE(10) RPCA_CASE(11) RPCA_CASE(12)
+        RPCA_CASE(13) RPCA_CASE(14) RPCA_CASE(15) RPCA_CASE(16)
+#undef RPCA_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t materialize_dispatch(const MaterializeArgs& a, int K, hipStream_t s) {
+    const dim3 grid((unsigned)((a.n + 255) / 256), (unsigned)(a.m < 4096 ? a.m : 4096)), block(256);
+    switch (K) {
+#define RPCA_CASE(KK) case KK: hipLaunchKernelGGL((k_materialize<T, KK>), grid, block, 0, s, a); break;
+        RPCA_CASE(1) RPCA_CASE(2) RPCA_CASE(3) RPCA_CASE(4) RPCA_CASE(5) RPCA_CASE(6)
+        RPCA_CASE(7) RPCA_CASE(8) RPCA_CASE(9) RPCA_CASE(10) RPCA_CASE(11) RPCA_CASE(12)
+        RPCA_CASE(13) RPCA_CASE(14) RPCA_CASE(15) RPCA_CASE(16)
+#undef RPCA_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, bool REBUILD>
+int stream_occupancy_t(int K) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (K) {
+#define RPCA_CASE(KK)                                                                                   \
+    case KK:                                                                                            \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stream<T, KK, REBUILD>, STREAM_THREADS, 0); \
+        break;
+        RPCA_CASE(1) RPCA_CASE(2) RPCA_CASE(3) RPCA_CASE(4) RPCA_CASE(5) RPCA_CASE(6)
+        RPCA_CASE(7) RPCA_CASE(8) RPCA_CASE(9) RPCA_CASE(10) RPCA_CASE(11) RPCA_CASE(12)
+        RPCA_CASE(13) RPCA_CASE(14) RPCA_CASE(15) RPCA_CASE(16)
+#undef RPCA_CASE
+        default: break;
+    }
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+}  // namespace
+
+int stream_occupancy(int K, int dtype, bool rebuild) {
+    if (dtype == 1) return rebuild ? stream_occupancy_t<float, true>(K) : stream_occupancy_t<float, false>(K);
+    return rebuild ? stream_occupancy_t<double, true>(K) : stream_occupancy_t<double, false>(K);
+}
+
+hipError_t launch_stream(const StreamArgs& a, int K, int dtype, bool rebuild, hipStream_t s) {
+    if (dtype == 1) return rebuild ? stream_dispatch<float, true>(a, K, s) : stream_dispatch<float, false>(a, K, s);
+    return rebuild ? stream_dispatch<double, true>(a, K, s) : stream_dispatch<double, false>(a, K, s);
+}
+
+hipError_t launch_materialize(const MaterializeArgs& a, int K, int dtype, hipStream_t s) {
+    if (dtype == 1) return materialize_dispatch<float>(a, K, s);
+    return materialize_dispatch<double>(a, K, s);
+}
+
+}  // namespace rpca

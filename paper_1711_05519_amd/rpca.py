@@ -1,0 +1,292 @@
+"""Thin Python binding of librpca (include/rpca.h).
+
+Argument marshalling only: every computation runs in the HIP library. Device
+buffers are torch CUDA tensors (ROCm build), passed by data pointer together
+with torch's current stream. The functions keep the C names:
+
+    rpca_workspace_size, rpca_init, rpca_trim, rpca_step, rpca_solve,
+    rpca_materialize, rpca_tangent_products
+
+`Solver` bundles the parameter struct, the iterate buffers and the workspace.
+There is no fallback: if the library is missing or no gfx950 device is
+current, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librpca.so")
+
+RPCA_OK, RPCA_MAXITER = 0, 1
+RPCA_F64, RPCA_F32 = 0, 1
+RPCA_FLAG_NO_TRIM = 1
+RPCA_MAX_RANK = 16
+
+EXPORTED = ("rpca_workspace_size", "rpca_init", "rpca_trim", "rpca_step", "rpca_solve",
+            "rpca_materialize", "rpca_tangent_products", "rpca_strerror",
+            "rpca_last_hip_error", "rpca_version", "rpca_profile_enable", "rpca_profile_read")
+
+
+class RpcaError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib().rpca_strerror(status).decode()
+        if status == -3:
+            msg += f" (hipError {_lib().rpca_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [status {status}]")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("ldd", ctypes.c_int64),
+                ("r", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("beta", ctypes.c_double), ("beta_init", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("mu", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("init_block", ctypes.c_int32),
+                ("init_max_passes", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("U", ctypes.c_void_p), ("V", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+                ("zeta", ctypes.c_double), ("err", ctypes.c_double),
+                ("sigma1_pt", ctypes.c_double), ("sigma_r1_pt", ctypes.c_double),
+                ("normD", ctypes.c_double), ("k", ctypes.c_int32), ("init_passes", ctypes.c_int32)]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built (python -m paper_1711_05519_amd.build)")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, S, vp, d = ctypes.POINTER(Params), ctypes.POINTER(State), ctypes.c_void_p, ctypes.c_double
+        pd = ctypes.POINTER(ctypes.c_double)
+        sz = ctypes.c_size_t
+        sig = {
+            "rpca_workspace_size": [P, ctypes.POINTER(sz)],
+            "rpca_init": [vp, P, S, vp, sz, vp],
+            "rpca_trim": [P, S, vp, vp, vp, sz, vp],
+            "rpca_step": [vp, P, S, vp, sz, vp],
+            "rpca_solve": [vp, P, S, pd, pd, ctypes.c_int32, vp, sz, vp],
+            "rpca_materialize": [vp, P, S, vp, ctypes.c_int64, vp, ctypes.c_int64, vp, sz, vp],
+            "rpca_tangent_products": [vp, P, vp, vp, d, vp, vp, vp, vp, pd, vp, sz, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        lib.rpca_strerror.argtypes = [ctypes.c_int]
+        lib.rpca_strerror.restype = ctypes.c_char_p
+        lib.rpca_last_hip_error.restype = ctypes.c_int
+        lib.rpca_version.restype = ctypes.c_int
+        lib.rpca_profile_enable.argtypes = [ctypes.c_int]
+        lib.rpca_profile_enable.restype = ctypes.c_int
+        lib.rpca_profile_read.argtypes = [pd, ctypes.POINTER(ctypes.c_int64)]
+        lib.rpca_profile_read.restype = ctypes.c_int
+        _LIB = lib
+    return _LIB
+
+
+def library():
+    """The loaded ctypes library (loads it on first use)."""
+    return _lib()
+
+
+def _check(status: int, where: str) -> int:
+    if status < 0:
+        raise RpcaError(status, where)
+    return status
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ws(ws: torch.Tensor):
+    return ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel() * ws.element_size())
+
+
+# ---- the C entry points ------------------------------------------------------
+
+def rpca_workspace_size(params: Params) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib().rpca_workspace_size(ctypes.byref(params), ctypes.byref(n)), "rpca_workspace_size")
+    return int(n.value)
+
+
+def rpca_init(D, params, state, ws, stream=None) -> int:
+    w, nb = _ws(ws)
+    return _check(_lib().rpca_init(_ptr(D), ctypes.byref(params), ctypes.byref(state), w, nb, _stream(stream)),
+                  "rpca_init")
+
+
+def rpca_trim(params, state, U_tilde, V_tilde, ws, stream=None) -> int:
+    w, nb = _ws(ws)
+    return _check(_lib().rpca_trim(ctypes.byref(params), ctypes.byref(state), _ptr(U_tilde), _ptr(V_tilde),
+                                   w, nb, _stream(stream)), "rpca_trim")
+
+
+def rpca_step(D, params, state, ws, stream=None) -> int:
+    w, nb = _ws(ws)
+    return _check(_lib().rpca_step(_ptr(D), ctypes.byref(params), ctypes.byref(state), w, nb, _stream(stream)),
+                  "rpca_step")
+
+
+def rpca_solve(D, params, state, err_hist, zeta_hist, ws, stream=None) -> int:
+    """err_hist / zeta_hist: ctypes double arrays (or None)."""
+    w, nb = _ws(ws)
+    cap = 0 if err_hist is None else len(err_hist)
+    return _check(_lib().rpca_solve(_ptr(D), ctypes.byref(params), ctypes.byref(state), err_hist, zeta_hist,
+                                    cap, w, nb, _stream(stream)), "rpca_solve")
+
+
+def rpca_materialize(D, params, state, L_out, S_out, ws, stream=None) -> int:
+    w, nb = _ws(ws)
+    ldl = 0 if L_out is None else L_out.stride(0)
+    lds = 0 if S_out is None else S_out.stride(0)
+    return _check(_lib().rpca_materialize(_ptr(D), ctypes.byref(params), ctypes.byref(state), _ptr(L_out), ldl,
+                                          _ptr(S_out), lds, w, nb, _stream(stream)), "rpca_materialize")
+
+
+def rpca_tangent_products(D, params, A_L, B_L, zeta, U_t, V_t, Y1, Y2, ws, stream=None) -> float:
+    w, nb = _ws(ws)
+    out = ctypes.c_double(0.0)
+    _check(_lib().rpca_tangent_products(_ptr(D), ctypes.byref(params), _ptr(A_L), _ptr(B_L), float(zeta),
+                                        _ptr(U_t), _ptr(V_t), _ptr(Y1), _ptr(Y2), ctypes.byref(out), w, nb,
+                                        _stream(stream)), "rpca_tangent_products")
+    return float(out.value)
+
+
+def rpca_profile_enable(on: bool) -> None:
+    _check(_lib().rpca_profile_enable(1 if on else 0), "rpca_profile_enable")
+
+
+def rpca_profile_read() -> tuple[float, int]:
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(_lib().rpca_profile_read(ctypes.byref(ms), ctypes.byref(n)), "rpca_profile_read")
+    return float(ms.value), int(n.value)
+
+
+# ---- convenience wrapper -----------------------------------------------------
+
+@dataclasses.dataclass
+class SolveInfo:
+    status: int
+    iterations: int
+    err: float
+    zeta: float
+    err_hist: list
+    zeta_hist: list
+    init_passes: int
+
+
+def make_params(D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: float, mu: float,
+                tol: float = 1e-5, max_iter: int = 100, trim: bool = True, init_block: int = 0,
+                init_max_passes: int = 0, seed: int = 0) -> Params:
+    if D.dim() != 2 or D.stride(1) != 1:
+        raise ValueError("D must be a 2-D row-major tensor with unit column stride")
+    if D.dtype == torch.float64:
+        dt = RPCA_F64
+    elif D.dtype == torch.float32:
+        dt = RPCA_F32
+    else:
+        raise ValueError("D must be float32 or float64")
+    return Params(m=D.shape[0], n=D.shape[1], ldd=D.stride(0), r=int(r), dtype=dt, beta=float(beta),
+                  beta_init=float(beta_init), gamma=float(gamma), mu=float(mu) if trim else 0.0, tol=float(tol),
+                  max_iter=int(max_iter), init_block=int(init_block), init_max_passes=int(init_max_passes),
+                  flags=0 if trim else RPCA_FLAG_NO_TRIM, seed=int(seed))
+
+
+class Solver:
+    """Owns the iterate buffers (U, sigma, V in FP64) and the workspace for one D."""
+
+    def __init__(self, D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: float, mu: float,
+                 tol: float = 1e-5, max_iter: int = 100, trim: bool = True, init_block: int = 0,
+                 init_max_passes: int = 0, seed: int = 0):
+        if not D.is_cuda:
+            raise ValueError("D must be a device tensor")
+        self.D = D
+        self.params = make_params(D, r, beta, beta_init, gamma, mu, tol, max_iter, trim, init_block,
+                                  init_max_passes, seed)
+        dev = D.device
+        m, n = D.shape
+        self.U = torch.zeros((m, r), dtype=torch.float64, device=dev)
+        self.V = torch.zeros((n, r), dtype=torch.float64, device=dev)
+        self.sigma = torch.zeros((r,), dtype=torch.float64, device=dev)
+        nbytes = rpca_workspace_size(self.params)
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws = raw[off:off + nbytes]
+        self.state = State(U=self.U.data_ptr(), V=self.V.data_ptr(), sigma=self.sigma.data_ptr(),
+                           zeta=0.0, err=float("nan"), sigma1_pt=0.0, sigma_r1_pt=0.0, normD=0.0, k=0,
+                           init_passes=0)
+
+    # state as host values / tensors
+    def set_state(self, U, sigma, V, zeta: float, k: int, normD: float = 0.0):
+        def host(a):
+            return a if isinstance(a, torch.Tensor) else torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64)
+        self.U.copy_(host(U))
+        self.V.copy_(host(V))
+        self.sigma.copy_(host(sigma))
+        self.state.zeta = float(zeta)
+        self.state.k = int(k)
+        self.state.normD = float(normD)
+        self.state.err = float("nan")
+
+    def init(self) -> None:
+        rpca_init(self.D, self.params, self.state, self.ws)
+
+    def step(self) -> None:
+        rpca_step(self.D, self.params, self.state, self.ws)
+
+    def trim(self):
+        m, n = self.D.shape
+        r = self.params.r
+        Ut = torch.empty((m, r), dtype=torch.float64, device=self.D.device)
+        Vt = torch.empty((n, r), dtype=torch.float64, device=self.D.device)
+        rpca_trim(self.params, self.state, Ut, Vt, self.ws)
+        return Ut, Vt
+
+    def solve(self) -> SolveInfo:
+        cap = self.params.max_iter + 1
+        eh = (ctypes.c_double * cap)()
+        zh = (ctypes.c_double * cap)()
+        st = rpca_solve(self.D, self.params, self.state, eh, zh, self.ws)
+        k = self.state.k
+        return SolveInfo(status=st, iterations=k, err=self.state.err, zeta=self.state.zeta,
+                         err_hist=list(eh[:k + 1]), zeta_hist=list(zh[:k + 1]),
+                         init_passes=self.state.init_passes)
+
+    def materialize(self, want_L: bool = True, want_S: bool = True):
+        L = torch.empty_like(self.D) if want_L else None
+        S = torch.empty_like(self.D) if want_S else None
+        rpca_materialize(self.D, self.params, self.state, L, S, self.ws)
+        return L, S
+
+    def tangent_products(self, A_L, B_L, zeta, U_t, V_t):
+        m, n = self.D.shape
+        r = self.params.r
+        Y1 = torch.empty((m, r), dtype=torch.float64, device=self.D.device)
+        Y2 = torch.empty((n, r), dtype=torch.float64, device=self.D.device)
+        res = rpca_tangent_products(self.D, self.params, A_L.contiguous(), B_L.contiguous(), zeta,
+                                    U_t.contiguous(), V_t.contiguous(), Y1, Y2, self.ws)
+        return Y1, Y2, res
+
+    def L_factors(self):
+        return self.U, self.sigma, self.V
