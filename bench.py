@@ -158,6 +158,7 @@ def main():
                          f"r={x.r} alpha={x.alpha} c={x.c}, FP32 D, stop at err<{x.tol:g}"),
             "iterations": info.iterations,
             "init_passes": info.init_passes,
+            "svd_sweeps_per_solve": info.svd_sweeps,
             "passes_per_solve": passes_per_solve,
             "final_err": info.err,
             "recovery_rel_err": recovery,

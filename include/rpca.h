@@ -90,6 +90,8 @@ typedef struct rpca_state {
                               when > 0 and otherwise spends one extra pass computing it      */
     int32_t  k;            /* iteration index                                                */
     int32_t  init_passes;  /* passes over D spent by rpca_init (diagnostic)                  */
+    int32_t  svd_sweeps;   /* Jacobi sweeps of all 2K x 2K SVDs in the last call (diagnostic) */
+    int32_t  reserved;     /* zero                                                           */
 } rpca_state;
 
 /* Bytes of device workspace needed by every entry point for these params.

@@ -213,7 +213,7 @@ Layout make_layout(const rpca_params* p) {
     L.n_rt_max = n_rt_for(m, L.n_ct, STREAM_MAX_SLOTS);
     L.gU = (m + PANEL_THREADS - 1) / PANEL_THREADS;
     L.gV = (n + PANEL_THREADS - 1) / PANEL_THREADS;
-    const int rpb = PANEL_THREADS / GATHER_SPLIT;   // the gather kernel's workgroups own fewer rows
+    const int rpb = GATHER_THREADS / GATHER_SPLIT;
     const int g_gather = (m + rpb - 1) / rpb + (n + rpb - 1) / rpb;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
@@ -223,7 +223,7 @@ Layout make_layout(const rpca_params* p) {
     L.off_P1 = take((size_t)L.n_ct * m * L.KW * L.acc);
     L.off_P2 = take((size_t)L.n_rt_max * n * L.KW * L.acc);
     L.off_resid = take(sizeof(double) * (size_t)L.n_ct * L.n_rt_max);
-    L.off_gpart = take(sizeof(double) * (size_t)(g_gather > L.gU + L.gV ? g_gather : L.gU + L.gV) * KMAX * KMAX);
+    L.off_gpart = take(sizeof(double) * (size_t)(g_gather > L.gU + L.gV ? g_gather : L.gU + L.gV) * GPART_STRIDE);
     const size_t pm = sizeof(double) * (size_t)m * L.KW, pn = sizeof(double) * (size_t)n * L.KW;
     L.off_Y1 = take(pm); L.off_Y2 = take(pn);
     L.off_W1 = take(pm); L.off_W2 = take(pn);
@@ -289,6 +289,8 @@ Ctrl base_ctrl(const Ctx& c, int stage, double zeta, int k, double normD2, int w
     t.res_prev = 1e300;
     t.tol_res_a = p->dtype == RPCA_F64 ? 1e-9 : 3e-6;
     t.tol_res_b = p->dtype == RPCA_F64 ? 1e-13 : 3e-6;
+    // rounding level of the streamed products relative to sigma_1
+    t.sigma_dead = p->dtype == RPCA_F64 ? 1e-12 : 1e-5;
     return t;
 }
 
@@ -368,10 +370,12 @@ int setup(const Ctx& c, const Ctrl& t) {
     return RPCA_OK;
 }
 
-// One loop body: stream pass, gather, complement, update (from M), basis.
+// One loop body. FP32: stream pass, gather (with the 2r x 2r step), update.
+// FP64: stream pass, gather, complement (explicit W), update.
 int enqueue_body(const Ctx& c, const void* D, int K, int body, double* state_U, double* state_V,
                  double* state_sigma, bool with_hist) {
     const bool rebuild = body != BODY_INIT;
+    const bool fp32 = c.dtype == RPCA_F32;
     const Geo g = geo_for(c, K, rebuild);
     StreamArgs sa = stream_args(c, D, body, g);
     RPCA_TRY(stream_launch(sa, K, c.dtype, rebuild, c.s));
@@ -382,10 +386,13 @@ int enqueue_body(const Ctx& c, const void* D, int K, int body, double* state_U, 
         pa.zeta_hist = c.zeta_hist();
         pa.hist_cap = c.p->max_iter + 1;
     }
+    pa.mode = fp32 ? GATHER_WITH_SVD : GATHER_ONLY;
     HIP_TRY(launch_gather(pa, K, c.dtype, c.s));
-    HIP_TRY(launch_complement(pa, K, c.dtype, c.s));
+    if (!fp32) HIP_TRY(launch_complement(pa, K, c.dtype, c.s));
     PanelArgs ua = pa;
     ua.mode = UPDATE_FROM_M;
+    ua.S2U = fp32 ? pa.Y1 : pa.W1;
+    ua.S2V = fp32 ? pa.Y2 : pa.W2;
     if (body == BODY_INIT) {
         ua.Unew = c.at<double>(c.L.off_Unew);
         ua.Vnew = c.at<double>(c.L.off_Vnew);
@@ -395,17 +402,13 @@ int enqueue_body(const Ctx& c, const void* D, int K, int body, double* state_U, 
         ua.sigma_dst = state_sigma;
     }
     HIP_TRY(launch_update(ua, K, c.dtype, c.s));
-    PanelArgs ba = pa;
-    ba.gated = 1;
-    HIP_TRY(launch_basis(ba, K, c.dtype, c.s));
     return RPCA_OK;
 }
 
-// Enter the loop from factors src (stride ld_src) with singular values src_sigma:
-// rebuild factors, Trim, and orthonormal bases. Optional FP64 copies of the bases.
+// Enter the loop from factors src (stride ld_src) with singular values
+// src_sigma: rebuild factors, Trim and the bases of the next streaming pass.
 int enqueue_enter(const Ctx& c, const double* srcU, const double* srcV, int64_t ld_src,
-                  const double* src_sigma, double* dstU, double* dstV, double* dst_sigma, double* outU,
-                  double* outV) {
+                  const double* src_sigma, double* dstU, double* dstV, double* dst_sigma) {
     const int K = c.p->r;
     PanelArgs ua = panel_args(c);
     ua.mode = UPDATE_ENTER;
@@ -417,11 +420,6 @@ int enqueue_enter(const Ctx& c, const double* srcU, const double* srcV, int64_t 
     ua.Vnew = dstV;
     ua.sigma_dst = dst_sigma;
     HIP_TRY(launch_update(ua, K, c.dtype, c.s));
-    PanelArgs ba = panel_args(c);
-    ba.gated = 0;
-    ba.outU = outU;
-    ba.outV = outV;
-    HIP_TRY(launch_basis(ba, K, c.dtype, c.s));
     return RPCA_OK;
 }
 
@@ -469,10 +467,7 @@ int run_init(const Ctx& c, const void* D, rpca_state* st, Ctrl* ctrl_out) {
     RPCA_TRY(setup(c, t));
     PanelArgs sa = panel_args(c);
     sa.seed = c.p->seed;
-    HIP_TRY(launch_start(sa, P, c.s));
-    PanelArgs ba = panel_args(c);
-    ba.gated = 0;
-    HIP_TRY(launch_basis(ba, P, c.dtype, c.s));
+    HIP_TRY(launch_start(sa, P, c.dtype, c.s));
     const int max_bodies = 2 * t.init_max_passes + 4;
     int rc = pipelined_loop(
         c, max_bodies,
@@ -484,7 +479,7 @@ int run_init(const Ctx& c, const void* D, rpca_state* st, Ctrl* ctrl_out) {
     if (now.stage < STAGE_INIT_DONE) return RPCA_EHIP;   // unreachable: the pass cap forces convergence
     // L_0: the leading r columns of the converged block
     RPCA_TRY(enqueue_enter(c, c.at<double>(c.L.off_Unew), c.at<double>(c.L.off_Vnew), P,
-                           c.small()->sigma_new, st->U, st->V, st->sigma, nullptr, nullptr));
+                           c.small()->sigma_new, st->U, st->V, st->sigma));
     *ctrl_out = now;
     return RPCA_OK;
 }
@@ -506,6 +501,7 @@ void fill_state(rpca_state* st, const Ctrl& t) {
     st->sigma1_pt = t.sig1_pt;
     st->sigma_r1_pt = t.sigr1_pt;
     st->normD = sqrt(t.normD2);
+    st->svd_sweeps = t.jacobi_sweeps;
 }
 
 int check_state(const rpca_state* st) {
@@ -614,7 +610,17 @@ int rpca_trim(const rpca_params* p, const rpca_state* st, double* U_tilde, doubl
     Ctx c;
     RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
     RPCA_TRY(setup(c, base_ctrl(c, STAGE_MAIN, st->zeta, st->k, 1.0, 0)));
-    RPCA_TRY(enqueue_enter(c, st->U, st->V, p->r, st->sigma, nullptr, nullptr, nullptr, U_tilde, V_tilde));
+    PanelArgs ua = panel_args(c);
+    ua.mode = UPDATE_ENTER_EXACT;
+    ua.srcU = st->U;
+    ua.srcV = st->V;
+    ua.ld_src = p->r;
+    ua.src_sigma = st->sigma;
+    HIP_TRY(launch_update(ua, p->r, c.dtype, c.s));
+    PanelArgs ba = panel_args(c);
+    ba.outU = U_tilde;
+    ba.outV = V_tilde;
+    HIP_TRY(launch_basis(ba, p->r, c.dtype, c.s));
     HIP_TRY(hipStreamSynchronize(c.s));
     return RPCA_OK;
 }
@@ -642,7 +648,7 @@ int rpca_step(const void* D, const rpca_params* p, rpca_state* st, void* ws, siz
     RPCA_TRY(setup(c, base_ctrl(c, STAGE_MAIN, st->zeta, st->k, nd2, 0)));
     const int K = p->r;
     // Trim(L_k) and its orthonormal bases
-    RPCA_TRY(enqueue_enter(c, st->U, st->V, K, st->sigma, nullptr, nullptr, nullptr, nullptr, nullptr));
+    RPCA_TRY(enqueue_enter(c, st->U, st->V, K, st->sigma, nullptr, nullptr, nullptr));
     // products with Z_k, the 2r x 2r update, zeta_{k+1}; L_{k+1} overwrites the state
     RPCA_TRY(enqueue_body(c, D, K, BODY_ANY, st->U, st->V, st->sigma, false));
     // err_{k+1}: threshold pass at (L_{k+1}, zeta_{k+1})

@@ -14,7 +14,9 @@ constexpr int STREAM_WAVES = STREAM_THREADS / WAVE;
 constexpr int STREAM_CPL = 4;     // consecutive columns owned by one lane
 constexpr int STREAM_TN = WAVE * STREAM_CPL;   // columns per stream tile
 constexpr int PANEL_THREADS = 256;
-constexpr int GATHER_SPLIT = 4;   // threads sharing one row in the gather kernel
+constexpr int GATHER_SPLIT = 4;   // adjacent lanes sharing one row in the gather kernel
+constexpr int GATHER_THREADS = 1024;
+constexpr int GPART_STRIDE = 2 * KMAX * KMAX;   // doubles per workgroup partial slot
 
 // Stages of the device-side state machine (Ctrl::stage).
 enum Stage : int {
@@ -75,6 +77,7 @@ struct Ctrl {
     double sig1_pt, sigr1_pt;   // sigma_1 and sigma_{r+1} of the last P_T(D - S_k)
     double tol_res_a, tol_res_b;
     double resid2;       // last residual sum (sum over |x| <= zeta of x^2)
+    double sigma_dead;   // relative size below which a singular triplet of M is dropped
 };
 
 // Small FP64 matrices shared between kernels (all K x K, row-major, ld = KMAX).
@@ -82,10 +85,11 @@ struct Small {
     double RUinv[KMAX * KMAX];   // R_U^{-1}: Gram(U_f) = R_U^T R_U
     double RVinv[KMAX * KMAX];
     double Cstar[KMAX * KMAX];   // C* = R_U^{-T} U_f^T Y1 R_V^{-1}
-    double X1[KMAX * KMAX];      // U_new = U* X1 + W1 X2
-    double X2[KMAX * KMAX];
-    double Z1[KMAX * KMAX];      // V_new = V* Z1 + W2 Z2
-    double Z2[KMAX * KMAX];
+    double C2[KMAX * KMAX];      // C2 = R_V^{-T} V_f^T Y2 R_U^{-1}  (= C*^T up to rounding)
+    double E1[KMAX * KMAX];      // U_new = U_f E1 + S_U E2  (S_U = Y1 or W1)
+    double E2[KMAX * KMAX];
+    double F1[KMAX * KMAX];      // V_new = V_f F1 + S_V F2  (S_V = Y2 or W2)
+    double F2[KMAX * KMAX];
     double RAinv[KMAX * KMAX];   // Gram(A) = R_A^T R_A (Trim output)
     double RBinv[KMAX * KMAX];
     double sigma_new[KMAX];
@@ -100,16 +104,21 @@ template <typename T> struct AccOf;
 template <> struct AccOf<float> { using type = float; };
 template <> struct AccOf<double> { using type = double; };
 
-// Sum of one double over the 256 threads of a workgroup (result valid in all threads).
-__device__ inline double block_sum_256(double v, double* red /* >= 4 doubles shared */) {
+// Sum of one double over the threads of a workgroup (result valid in all
+// threads; fixed order). red: shared scratch of blockDim.x / 64 doubles.
+__device__ inline double block_sum(double v, double* red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
     const int w = threadIdx.x / WAVE;
+    const int nw = blockDim.x / WAVE;
     __syncthreads();
     if ((threadIdx.x & (WAVE - 1)) == 0) red[w] = v;
     __syncthreads();
-    double s = red[0] + red[1] + red[2] + red[3];
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    __syncthreads();
     return s;
 }
+__device__ inline double block_sum_256(double v, double* red) { return block_sum(v, red); }
 
 // Whether a streaming pass / gather launch of the given body executes.
 __device__ inline bool body_runs(const Ctrl* c, int body) {

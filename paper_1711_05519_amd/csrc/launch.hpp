@@ -60,6 +60,7 @@ struct PanelArgs {
     double* W1; double* W2;
     double* Ap; double* Bp;   // trimmed factors / blocks to orthonormalise
     double* Unew; double* Vnew;  // destinations of the updated factors (stride K)
+    const double* S2U; const double* S2V;  // second panels of the update (Y or W)
     double* sigma_dst;        // destination of sigma_new (nullable)
     // T-typed panels
     void* Uf; void* Vf;       // bases used by the stream pass
@@ -77,7 +78,8 @@ struct PanelArgs {
     int32_t gated;            // basis kernel: skip when the body is not active
 };
 
-enum UpdateMode : int { UPDATE_FROM_M = 0, UPDATE_ENTER = 1 };
+enum UpdateMode : int { UPDATE_FROM_M = 0, UPDATE_ENTER = 1, UPDATE_ENTER_EXACT = 2 };
+enum GatherMode : int { GATHER_ONLY = 0, GATHER_WITH_SVD = 1 };
 
 // dtype: 0 = double, 1 = float
 // Workgroups of the streaming pass resident per CU (from the HIP occupancy API).
@@ -88,7 +90,7 @@ hipError_t launch_gather(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_complement(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_update(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_basis(const PanelArgs& a, int K, int dtype, hipStream_t s);
-hipError_t launch_start(const PanelArgs& a, int K, hipStream_t s);
+hipError_t launch_start(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, hipStream_t s);
 hipError_t launch_convert(const double* src, void* dst, int64_t count, const double* scale, int K,
                           int dtype, hipStream_t s);

@@ -1,44 +1,46 @@
 // Tall-skinny (m x K, n x K) FP64 panel kernels between two streaming passes,
 // and the small K x K / 2K x 2K FP64 linear algebra of Section 2.1.
 //
-// Every panel kernel runs one thread per row over the m rows of the U side and
-// the n rows of the V side in one grid. Reductions over rows (Gram matrices,
-// U_f^T Y1) are written as per-workgroup partials; the workgroup that
-// finishes last (atomic arrival counter + device-scope fences) sums them in a
-// fixed order and runs the small dense algebra, so results are deterministic.
+// Row phases run one thread per row (four lanes per row in the gather) over
+// the m rows of the U side and the n rows of the V side in one grid. Sums over
+// rows (Grams, U_f^T Y1) are written as per-workgroup partials; the workgroup
+// that arrives last (atomic counter + device-scope fences) keeps a single wave
+// that sums them in a fixed order and runs the small dense algebra with
+// wave-level synchronisation only, so results are deterministic and the
+// serial tail has no block barriers.
 //
-// Notation (k-th iteration, K = r in the loop and K = p in the initialisation):
-//   U_f, V_f   bases used by the streaming pass (dtype of D)
-//   R_U, R_V   Cholesky factors of Gram(U_f), Gram(V_f); U* = U_f R_U^{-1} and
+// Notation (iteration k; K = r in the loop and K = p in the initialisation):
+//   U_f, V_f   bases read by the streaming pass (dtype of D)
+//   R_U, R_V   Cholesky factors of Gram(U_f), Gram(V_f); U* = U_f R_U^{-1},
 //              V* = V_f R_V^{-1} are orthonormal to FP64 accuracy and span the
-//              same spaces, so the FP32 rounding of the bases never breaks the
-//              orthogonality the 2r x 2r reduction relies on
-//   Y1 = Z V_f, Y2 = Z^T U_f                (streaming pass, Z = D - S_k)
-//   C*  = U*^T Z V*                         top-left block of M
+//              same spaces (a Cholesky QR whose R is applied implicitly), so
+//              rounding the bases to FP32 never breaks the orthogonality the
+//              2r x 2r reduction relies on
+//   Y1 = Z V_f, Y2 = Z^T U_f                   (streaming pass, Z = D - S_k)
+//   C*  = U*^T Z V*,  C2 = V*^T Z^T U*          (C2 = C*^T up to rounding)
 //   W1  = (I - U* U*^T) Z V* = Q1 R1,  W2 = (I - V* V*^T) Z^T U* = Q2 R2
 //   M   = [[C*, R2^T], [R1, 0]] = U_M Sigma_M V_M^T   (one-sided Jacobi)
-//   U_{k+1} = [U* Q1] U_M[:, :K] = U* X1 + W1 X2,  X2 = R1^{-1} U_M[K:, :K]
-//   V_{k+1} = [V* Q2] V_M[:, :K] = V* Z1 + W2 Z2,  Z2 = R2^{-1} V_M[K:, :K]
-// Q1 and Q2 are never formed.
+//   U_{k+1} = [U* Q1] U_M[:, :K],  V_{k+1} = [V* Q2] V_M[:, :K]
+// Q1, Q2 are never formed: U_{k+1} = U_f E1 + S_U E2 with small coefficient
+// matrices, S_U = W1 (FP64 path) or Y1 (FP32 path, where Gram(W1) is formed
+// as Gram(Y1*) - C*^T C*, exact to the FP32 level of the products).
 #include "launch.hpp"
 
 namespace rpca {
 namespace {
 
 constexpr double JACOBI_EPS = 1e-15;
+// Pairs with |a_p . a_q| <= JACOBI_ABS ||M||_F^2 are left alone: such a coupling
+// moves the leading singular vectors by about that relative amount, and the
+// trailing (negligible) columns would otherwise keep rotating on rounding noise.
+constexpr double JACOBI_ABS = 1e-17;
 constexpr int JACOBI_MAX_SWEEPS = 40;
 constexpr double CHOL_DEAD_REL = 1e-26;
 
-// ---- helpers -----------------------------------------------------------------
+template <typename T> __device__ inline T* tptr(void* p) { return static_cast<T*>(p); }
+template <typename T> __device__ inline const T* tptr(const void* p) { return static_cast<const T*>(p); }
 
-template <int K>
-__device__ inline void load_small(const double* __restrict__ g, double* s) {
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) s[e] = g[(e / K) * KMAX + (e % K)];
-}
-template <int K>
-__device__ inline void store_small(const double* s, double* __restrict__ g) {
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) g[(e / K) * KMAX + (e % K)] = s[e];
-}
+// ---- row-phase helpers (whole workgroup) --------------------------------------
 
 // y = x A for a row vector x (1 x K) and A (K x K, ld K, LDS)
 template <int K>
@@ -51,84 +53,128 @@ __device__ inline void rowmul(const double (&x)[K], const double* A, double (&y)
         y[j] = acc;
     }
 }
-// y = x A^T
+
 template <int K>
-__device__ inline void rowmul_t(const double (&x)[K], const double* A, double (&y)[K]) {
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        double acc = 0.0;
-#pragma unroll
-        for (int i = 0; i < K; ++i) acc = fma(x[i], A[j * K + i], acc);
-        y[j] = acc;
-    }
+__device__ inline void block_load_small(const double* __restrict__ g, double* s) {
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) s[e] = g[(e / K) * KMAX + (e % K)];
 }
 
-// Workgroup sum over threads of a (x) b -> dst[t1 * K + t2] (global, K*K entries).
-// sa, sb: LDS scratch of PANEL_THREADS*K doubles each.
-template <int K>
-__device__ void block_outer_sum(const double (&a)[K], const double (&b)[K], double* sa, double* sb,
-                                double* __restrict__ dst) {
+// Workgroup sum over NR row slots of a (x) b -> dst[t1 * K + t2] (global,
+// K*K entries). Exactly one thread per slot passes writer = true (zero vectors
+// for rows past the end). sa, sb: LDS scratch of NR*K doubles each; every
+// thread of the block must call it.
+template <int K, int NR>
+__device__ void rows_outer_sum(const double (&a)[K], const double (&b)[K], bool writer, int slot, double* sa,
+                               double* sb, double* __restrict__ dst) {
+    if (writer) {
 #pragma unroll
-    for (int t = 0; t < K; ++t) {
-        sa[threadIdx.x * K + t] = a[t];
-        sb[threadIdx.x * K + t] = b[t];
+        for (int t = 0; t < K; ++t) {
+            sa[slot * K + t] = a[t];
+            sb[slot * K + t] = b[t];
+        }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
         const int t1 = e / K, t2 = e % K;
         double acc = 0.0;
 #pragma unroll 8
-        for (int r = 0; r < PANEL_THREADS; ++r) acc = fma(sa[r * K + t1], sb[r * K + t2], acc);
+        for (int r = 0; r < NR; ++r) acc = fma(sa[r * K + t1], sb[r * K + t2], acc);
         dst[e] = acc;
     }
     __syncthreads();
 }
 
-// Fixed-order sum of partial blocks [first, first+count) of gpart into s (LDS,
-// K*K). Thread (e, g) sums the blocks b = g, g + G, ... of entry e with
-// several loads in flight; the G group sums are then added in group order.
-template <int K>
-__device__ void sum_partials(const double* gpart, int first, int count, double* s) {
-    constexpr int E = K * K;
-    constexpr int G = PANEL_THREADS / E > 0 ? PANEL_THREADS / E : 1;
-    __shared__ double tmp[G * E > PANEL_THREADS ? G * E : PANEL_THREADS];
-    const int e = threadIdx.x % E, g = threadIdx.x / E;
-    if (g < G) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        int b = g;
-        for (; b + 3 * G < count; b += 4 * G) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] += gpart[(size_t)(first + b + u * G) * KMAX * KMAX + e];
-        }
-        for (int u = 0; b < count; b += G, ++u) acc[u & 3] += gpart[(size_t)(first + b) * KMAX * KMAX + e];
-        tmp[g * E + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-    }
-    __syncthreads();
-    if (threadIdx.x < E) {
-        double t = 0.0;
-        for (int q = 0; q < G; ++q) t += tmp[q * E + threadIdx.x];
-        s[threadIdx.x] = t;
-    }
-    __syncthreads();
+// ---- single-wave helpers (the last workgroup's tail) ---------------------------
+
+__device__ inline int lane_id() { return threadIdx.x & (WAVE - 1); }
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
-// G = R^T R with R upper triangular (LDS, ld K), and Rinv = R^{-1}. A pivot
-// that vanishes (d <= CHOL_DEAD_REL * G_jj or G_jj ~ 0) marks a numerically
-// dependent column: its row of R and column of Rinv are set to zero.
 template <int K>
-__device__ void block_chol_inv(const double* G, double* R, double* Rinv) {
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) { R[e] = 0.0; Rinv[e] = 0.0; }
-    __syncthreads();
+__device__ inline void w_load(const double* __restrict__ g, double* s) {
+    for (int e = lane_id(); e < K * K; e += WAVE) s[e] = g[(e / K) * KMAX + (e % K)];
+    wave_sync();
+}
+template <int K>
+__device__ inline void w_store(const double* s, double* __restrict__ g) {
+    for (int e = lane_id(); e < K * K; e += WAVE) g[(e / K) * KMAX + (e % K)] = s[e];
+    wave_sync();
+}
+// C = op(A) B (K x K, ld K, LDS); op = transpose when TA
+template <int K, bool TA>
+__device__ inline void w_mm(const double* A, const double* B, double* C) {
+    for (int e = lane_id(); e < K * K; e += WAVE) {
+        const int i = e / K, j = e % K;
+        double acc = 0.0;
+        for (int l = 0; l < K; ++l) acc = fma(TA ? A[l * K + i] : A[i * K + l], B[l * K + j], acc);
+        C[e] = acc;
+    }
+    wave_sync();
+}
+
+// Fixed-order sum of partial blocks b in [first, first+count) of gpart (block b
+// at gpart + b*stride + off) into s (LDS, K*K entries). The wave first copies
+// a chunk of blocks to LDS with all its loads in flight at once (the caches
+// were just invalidated by the acquire fence, so every load goes to memory),
+// then lane e adds entry e of the chunk's blocks in block order.
+template <int K>
+__device__ void w_sum_partials(const double* gpart, int first, int count, int stride, int off, double* s) {
+    constexpr int E = K * K;
+    constexpr int PER_LANE = 16;
+    constexpr int CH = (WAVE * PER_LANE) / E;   // blocks per chunk
+    __shared__ double stage[CH * E];
+    const int lane = lane_id();
+    double run[(E + WAVE - 1) / WAVE];
+#pragma unroll
+    for (int u = 0; u < (E + WAVE - 1) / WAVE; ++u) run[u] = 0.0;
+    for (int b0 = 0; b0 < count; b0 += CH) {
+        const int nb = count - b0 < CH ? count - b0 : CH;
+        double v[PER_LANE];
+#pragma unroll
+        for (int u = 0; u < PER_LANE; ++u) {
+            const int i = lane + WAVE * u;         // i = block * E + entry within the chunk
+            v[u] = i < nb * E ? gpart[(size_t)(first + b0 + i / E) * stride + off + (i % E)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PER_LANE; ++u) {
+            const int i = lane + WAVE * u;
+            if (i < nb * E) stage[i] = v[u];
+        }
+        wave_sync();
+#pragma unroll
+        for (int u = 0; u < (E + WAVE - 1) / WAVE; ++u) {
+            const int e = lane + WAVE * u;
+            if (e < E)
+                for (int b = 0; b < nb; ++b) run[u] += stage[b * E + e];
+        }
+        wave_sync();
+    }
+#pragma unroll
+    for (int u = 0; u < (E + WAVE - 1) / WAVE; ++u) {
+        const int e = lane + WAVE * u;
+        if (e < E) s[e] = run[u];
+    }
+    wave_sync();
+}
+
+// G = R^T R with R upper triangular (LDS, ld K) and Rinv = R^{-1}; lane c
+// owns column c. A pivot that vanishes (d <= CHOL_DEAD_REL * G_jj or G_jj ~ 0)
+// marks a numerically dependent column: its row of R and column of Rinv are 0.
+template <int K>
+__device__ void w_chol_inv(const double* G, double* R, double* Rinv) {
+    const int c = lane_id();
+    for (int e = c; e < K * K; e += WAVE) R[e] = 0.0;
+    wave_sync();
     for (int j = 0; j < K; ++j) {
-        if (threadIdx.x == 0) {
+        if (c == j) {
             const double g = G[j * K + j];
             double d = g;
             for (int k = 0; k < j; ++k) d -= R[k * K + j] * R[k * K + j];
-            const bool alive = g > 1e-300 && d > CHOL_DEAD_REL * g;
-            R[j * K + j] = alive ? sqrt(d) : 0.0;
+            R[j * K + j] = (g > 1e-300 && d > CHOL_DEAD_REL * g) ? sqrt(d) : 0.0;
         }
-        __syncthreads();
-        const int c = threadIdx.x;
+        wave_sync();
         if (c > j && c < K) {
             const double rjj = R[j * K + j];
             double v = 0.0;
@@ -139,10 +185,9 @@ __device__ void block_chol_inv(const double* G, double* R, double* Rinv) {
             }
             R[j * K + c] = v;
         }
-        __syncthreads();
+        wave_sync();
     }
-    if (threadIdx.x < K) {
-        const int c = threadIdx.x;
+    if (c < K) {
         double x[K];
         for (int i = K - 1; i >= 0; --i) {
             const double rii = R[i * K + i];
@@ -156,7 +201,7 @@ __device__ void block_chol_inv(const double* G, double* R, double* Rinv) {
         }
         for (int i = 0; i < K; ++i) Rinv[i * K + c] = x[i];
     }
-    __syncthreads();
+    wave_sync();
 }
 
 template <int CTRL> __device__ inline double dpp64(double x) {
@@ -179,10 +224,11 @@ constexpr int pow2_floor(int x) { int p = 1; while (p * 2 <= x) p *= 2; return p
 // One-sided (Hestenes) Jacobi SVD of the N x N matrix A (LDS, column-major),
 // run by a single wave: the N/2 disjoint column pairs of a round-robin round
 // are processed at once, LP lanes per pair, with DPP reductions for the three
-// inner products. Sweeps stop when no pair needed a rotation
-// (|a_p . a_q| <= JACOBI_EPS ||a_p|| ||a_q||). On return sig[] is descending
-// and Uo/Vo hold left/right singular vectors as columns (column-major).
-// Must be called by all 64 lanes of one wave; returns the sweep count.
+// inner products. A pair is rotated when |a_p . a_q| > JACOBI_EPS ||a_p|| ||a_q||
+// and above the absolute floor JACOBI_ABS ||A||_F^2 (pairs of negligible
+// columns would otherwise rotate on rounding noise). Sweeps stop when no pair
+// was rotated. On return sig[] is descending and Uo/Vo hold the left/right
+// singular vectors as columns (column-major). Returns the sweep count.
 template <int N>
 __device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, double* Vo) {
     static_assert(N % 2 == 0 && N <= 2 * KMAX, "even N up to 2*KMAX");
@@ -190,10 +236,15 @@ __device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, do
     constexpr int LP0 = pow2_floor(WAVE / NP);
     constexpr int LP = LP0 > 16 ? 16 : LP0;
     constexpr int E = (N + LP - 1) / LP;
-    const int lane = threadIdx.x & (WAVE - 1);
-    for (int e = lane; e < N * N; e += WAVE) V[e] = ((e / N) == (e % N)) ? 1.0 : 0.0;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    const int lane = lane_id();
+    double fro = 0.0;
+    for (int e = lane; e < N * N; e += WAVE) {
+        V[e] = ((e / N) == (e % N)) ? 1.0 : 0.0;
+        fro = fma(A[e], A[e], fro);
+    }
+    for (int off = 32; off > 0; off >>= 1) fro += __shfl_xor(fro, off, WAVE);
+    const double floor_abs = JACOBI_ABS * fro;
+    wave_sync();
     const int q = lane / LP, g = lane % LP;
     int sweep = 0;
     for (; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
@@ -219,7 +270,7 @@ __device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, do
                 al = group_sum<LP>(al);
                 be = group_sum<LP>(be);
                 ga = group_sum<LP>(ga);
-                if (fabs(ga) > JACOBI_EPS * sqrt(al * be)) {
+                if (fabs(ga) > JACOBI_EPS * sqrt(al * be) && fabs(ga) > floor_abs) {
                     const double zt = (be - al) / (2.0 * ga);
                     const double t = fabs(zt) > 1e100 ? 0.5 / zt
                                                       : copysign(1.0, zt) / (fabs(zt) + sqrt(1.0 + zt * zt));
@@ -238,20 +289,17 @@ __device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, do
                     rotated = true;
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
         }
         if (!__any(rotated)) break;
     }
     // column norms, ranks (descending, ties by index), normalised outputs
     if (lane < N) {
-        const int j = lane;
         double acc = 0.0;
-        for (int e = 0; e < N; ++e) acc = fma(A[j * N + e], A[j * N + e], acc);
-        sig[j] = sqrt(acc);
+        for (int e = 0; e < N; ++e) acc = fma(A[lane * N + e], A[lane * N + e], acc);
+        sig[lane] = sqrt(acc);
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     double sj = 0.0;
     int rank = 0;
     if (lane < N) {
@@ -261,8 +309,7 @@ __device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, do
             rank += (si > sj) || (si == sj && i < lane);
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     if (lane < N) {
         sig[rank] = sj;
         const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
@@ -271,13 +318,9 @@ __device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, do
             Vo[rank * N + e] = V[lane * N + e];
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     return sweep + 1;
 }
-
-template <typename T> __device__ inline T* tptr(void* p) { return static_cast<T*>(p); }
-template <typename T> __device__ inline const T* tptr(const void* p) { return static_cast<const T*>(p); }
 
 __device__ inline void publish_status(const PanelArgs& a, const Ctrl* c) {
     if (a.host_status) {
@@ -293,25 +336,142 @@ __device__ inline void publish_status(const PanelArgs& a, const Ctrl* c) {
     }
 }
 
-// ---- kernel 1: gather partial products, U_f^T Y1, residual, stopping rule ----
+// ---- the 2K x 2K step shared by the FP32 gather and the FP64 complement ------
+//
+// Single wave. Given C*, C2, the Grams G1 = W1^T W1 and G2 = W2^T W2 and
+// R_U^{-1}, R_V^{-1}: R1, R2 by Cholesky, M = [[C*, R2^T], [R1, 0]], its SVD,
+// then either the next threshold (Algorithm 1) or the convergence test of the
+// initial subspace iteration, and the coefficients of the new factors
+//   U_{k+1} = U_f E1 + S_U E2,   V_{k+1} = V_f F1 + S_V F2,
+// with (S_U, S_V) = (Y1, Y2) when gram_form, (W1, W2) otherwise.
+template <int K>
+__device__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, const double* c2,
+                           const double* g1, const double* g2, const double* ru, const double* rv,
+                           bool gram_form) {
+    constexpr int N = 2 * K;
+    __shared__ double r1[K * K], r1i[K * K], r2[K * K], r2i[K * K];
+    __shared__ double Ma[N * N], Mv[N * N], Um[N * N], Vm[N * N], sg[N];
+    __shared__ double x1[K * K], x2[K * K], z1[K * K], z2[K * K], t1[K * K], t2[K * K];
+    const int lane = lane_id();
+    w_chol_inv<K>(g1, r1, r1i);
+    w_chol_inv<K>(g2, r2, r2i);
+    for (int e = lane; e < N * N; e += WAVE) {
+        const int col = e / N, rw = e % N;
+        double v = 0.0;
+        if (rw < K && col < K) v = cs[rw * K + col];
+        else if (rw < K) v = r2[(col - K) * K + rw];          // R2^T
+        else if (col < K) v = r1[(rw - K) * K + col];         // R1
+        Ma[e] = v;
+    }
+    wave_sync();
+    const int sweeps = wave_jacobi_svd<N>(Ma, Mv, sg, Um, Vm);
+    // Triplets whose singular value is at the rounding level of the products
+    // (sigma_j <= sigma_dead * sigma_1) carry no information about the range
+    // of P_T(Z): their vectors are noise and need not be orthogonal to U*, so
+    // they are dropped (zero columns) instead of entering the next basis.
+    const double cut = ctrl->sigma_dead * sg[0];
+    for (int e = lane; e < N * N; e += WAVE) {
+        if (sg[e / N] <= cut) { Um[e] = 0.0; Vm[e] = 0.0; }
+    }
+    wave_sync();
+    // X1 = U_M[:K, :K], X2 = R1^{-1} U_M[K:, :K]; Z1, Z2 likewise from V_M
+    for (int e = lane; e < K * K; e += WAVE) {
+        const int i = e / K, j = e % K;   // coefficient row i, singular triplet j
+        double xx = 0.0, zz = 0.0;
+        for (int l = 0; l < K; ++l) {
+            xx = fma(r1i[i * K + l], Um[j * N + K + l], xx);
+            zz = fma(r2i[i * K + l], Vm[j * N + K + l], zz);
+        }
+        x1[e] = Um[j * N + i];
+        z1[e] = Vm[j * N + i];
+        x2[e] = xx;
+        z2[e] = zz;
+    }
+    wave_sync();
+    Small* sm = a.small;
+    if (gram_form) {
+        // E1 = R_U^{-1} (X1 - C* X2), E2 = R_V^{-1} X2, F1 = R_V^{-1} (Z1 - C2 Z2), F2 = R_U^{-1} Z2
+        w_mm<K, false>(cs, x2, t1);
+        w_mm<K, false>(c2, z2, t2);
+        for (int e = lane; e < K * K; e += WAVE) { t1[e] = x1[e] - t1[e]; t2[e] = z1[e] - t2[e]; }
+        wave_sync();
+        w_mm<K, false>(ru, t1, x1);
+        w_mm<K, false>(rv, t2, z1);
+        w_mm<K, false>(rv, x2, t1);
+        w_mm<K, false>(ru, z2, t2);
+        w_store<K>(x1, sm->E1);
+        w_store<K>(t1, sm->E2);
+        w_store<K>(z1, sm->F1);
+        w_store<K>(t2, sm->F2);
+    } else {
+        // E1 = R_U^{-1} X1, E2 = X2, F1 = R_V^{-1} Z1, F2 = Z2
+        w_mm<K, false>(ru, x1, t1);
+        w_mm<K, false>(rv, z1, t2);
+        w_store<K>(t1, sm->E1);
+        w_store<K>(x2, sm->E2);
+        w_store<K>(t2, sm->F1);
+        w_store<K>(z2, sm->F2);
+    }
+    if (lane < N) sm->sigma_M[lane] = sg[lane];
+    if (lane < K) sm->sigma_new[lane] = sg[lane];
+    if (lane == 0) {
+        const int r = ctrl->r;
+        if (ctrl->stage == STAGE_MAIN) {
+            // zeta_{k+1} = beta (sigma_{r+1} + gamma^{k+1} sigma_1)  (Algorithm 1)
+            const int k = ctrl->k;
+            const double s1 = sg[0], sr1 = sg[r];
+            ctrl->sig1_pt = s1;
+            ctrl->sigr1_pt = sr1;
+            ctrl->zeta = ctrl->beta * (sr1 + pow(ctrl->gamma, (double)(k + 1)) * s1);
+            ctrl->k = k + 1;
+        } else {
+            // residual of the leading r directions of the previous block
+            double acc = 0.0;
+            for (int t = 0; t < r; ++t) acc += fmax(g1[t * K + t], 0.0) + fmax(g2[t * K + t], 0.0);
+            const double res = sg[0] > 0.0 ? sqrt(acc) / sg[0] : 0.0;
+            const double tolr = ctrl->stage == STAGE_SIGMA_D ? ctrl->tol_res_a : ctrl->tol_res_b;
+            const bool conv = res <= tolr || (ctrl->passes >= 3 && res > 0.5 * ctrl->res_prev) ||
+                              ctrl->passes >= ctrl->init_max_passes;
+            ctrl->res_prev = res;
+            if (conv && ctrl->stage == STAGE_SIGMA_D) {
+                ctrl->sigma1_D = sg[0];
+                ctrl->zeta = ctrl->beta_init * sg[0];     // zeta_{-1} = beta_init sigma_1(D)
+                ctrl->stage = STAGE_INIT_Z;
+                ctrl->passes = 0;
+                ctrl->res_prev = 1e300;
+            } else if (conv) {
+                ctrl->zeta = ctrl->beta * sg[0];          // zeta_0 = beta sigma_1(D - S_{-1})
+                ctrl->stage = STAGE_INIT_DONE;
+            }
+        }
+        ctrl->jacobi_sweeps += sweeps;
+        publish_status(a, ctrl);
+    }
+    wave_sync();
+}
 
+// ---- kernel 1: gather partial products, C*, residual, stopping rule ----------
+//
+// 1024 threads, four adjacent lanes per row: the lanes of a quad sum disjoint
+// subsets of the streaming-pass tiles, then a fixed-order quad reduction.
+// FP32 (gram_form): also the Grams of Y1 and Y2, and the whole 2K x 2K step in
+// the tail. FP64: only C* and C2; the complement kernel forms W explicitly.
 template <typename T, int K>
-__global__ __launch_bounds__(PANEL_THREADS) void k_gather(PanelArgs a) {
+__global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     using Acc = typename AccOf<T>::type;
-    constexpr int RPB = PANEL_THREADS / GATHER_SPLIT;   // rows per workgroup
+    constexpr int RPB = GATHER_THREADS / GATHER_SPLIT;   // rows per workgroup
+    constexpr bool GRAM = sizeof(T) == 4;
     Ctrl* ctrl = a.ctrl;
     if (!body_runs(ctrl, a.body)) return;
-    __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K];
-    __shared__ double part[PANEL_THREADS * K];
+    __shared__ double sa[RPB * K], sb[RPB * K];
     __shared__ int flag;
     const int gU = (a.m + RPB - 1) / RPB;
     const bool uside = (int)blockIdx.x < gU;
-    const int lr = threadIdx.x % RPB, chunk = threadIdx.x / RPB;
-    const int row = (uside ? blockIdx.x : blockIdx.x - gU) * RPB + lr;
+    const int slot = threadIdx.x / GATHER_SPLIT, chunk = threadIdx.x % GATHER_SPLIT;
+    const int row = (uside ? blockIdx.x : blockIdx.x - gU) * RPB + slot;
     const int nrows = uside ? a.m : a.n;
     const int ntiles = uside ? a.n_ct : a.n_rt;
     const Acc* P = tptr<Acc>(uside ? a.P1 : a.P2);
-    // this thread sums tiles c = chunk, chunk + SPLIT, ... of its row
     double y[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) y[t] = 0.0;
@@ -332,53 +492,59 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_gather(PanelArgs a) {
 #pragma unroll
             for (int t = 0; t < K; ++t) y[t] += static_cast<double>(P[((size_t)c * nrows + row) * K + t]);
     }
+    // quad reduction (lanes 4s..4s+3 hold the chunks of row s)
 #pragma unroll
-    for (int t = 0; t < K; ++t) part[threadIdx.x * K + t] = y[t];
-    __syncthreads();
-    // chunk 0 adds the chunk sums in chunk order
-    double uf[K];
+    for (int t = 0; t < K; ++t) {
+        y[t] += dpp64<0xB1>(y[t]);
+        y[t] += dpp64<0x4E>(y[t]);
+    }
+    const bool holder = chunk == 0 && row < nrows;
+    double f[K];   // the row of U_f (U side) or V_f (V side)
 #pragma unroll
-    for (int t = 0; t < K; ++t) { uf[t] = 0.0; y[t] = 0.0; }
-    if (chunk == 0 && row < nrows) {
-        for (int q = 0; q < GATHER_SPLIT; ++q)
-#pragma unroll
-            for (int t = 0; t < K; ++t) y[t] += part[(q * RPB + lr) * K + t];
+    for (int t = 0; t < K; ++t) f[t] = 0.0;
+    if (holder) {
         double* Y = uside ? a.Y1 : a.Y2;
 #pragma unroll
         for (int t = 0; t < K; ++t) Y[(size_t)row * K + t] = y[t];
-        if (uside) {
-            const T* Uf = tptr<T>(a.Uf);
+        const T* F = tptr<T>(uside ? a.Uf : a.Vf);
 #pragma unroll
-            for (int t = 0; t < K; ++t) uf[t] = static_cast<double>(Uf[(size_t)row * K + t]);
-        }
+        for (int t = 0; t < K; ++t) f[t] = static_cast<double>(F[(size_t)row * K + t]);
+    } else {
+#pragma unroll
+        for (int t = 0; t < K; ++t) y[t] = 0.0;
     }
-    if (uside) block_outer_sum<K>(uf, y, sa, sb, a.gpart + (size_t)blockIdx.x * KMAX * KMAX);
+    double* gp = a.gpart + (size_t)blockIdx.x * GPART_STRIDE;
+    const bool writer = chunk == 0;   // y and f are zero unless this lane holds a valid row
+    rows_outer_sum<K, RPB>(f, y, writer, slot, sa, sb, gp);      // U_f^T Y1 or V_f^T Y2
+    if (GRAM) rows_outer_sum<K, RPB>(y, y, writer, slot, sa, sb, gp + KMAX * KMAX);
     if (!last_block_arrives(&ctrl->cnt[CNT_GATHER], &flag)) return;
 
-    // ---- last workgroup ----
-    __shared__ double craw[K * K], ru[K * K], rv[K * K], tmp[K * K], red[4];
-    sum_partials<K>(a.gpart, 0, gU, craw);
-    load_small<K>(a.small->RUinv, ru);
-    load_small<K>(a.small->RVinv, rv);
-    __syncthreads();
-    // C* = R_U^{-T} Craw R_V^{-1}
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-        const int i = e / K, j = e % K;
-        double acc = 0.0;
-        for (int l = 0; l < K; ++l) acc = fma(craw[i * K + l], rv[l * K + j], acc);
-        tmp[e] = acc;
+    // ---- last workgroup: one wave from here on ----
+    if (threadIdx.x >= WAVE) return;
+    __shared__ double craw[K * K], craw2[K * K], ru[K * K], rv[K * K], cs[K * K], c2[K * K], tmp[K * K];
+    __shared__ double gy1[K * K], gy2[K * K], g1[K * K], g2[K * K];
+    const int lane = lane_id();
+    const int gV = gridDim.x - gU;
+    w_sum_partials<K>(a.gpart, 0, gU, GPART_STRIDE, 0, craw);
+    w_sum_partials<K>(a.gpart, gU, gV, GPART_STRIDE, 0, craw2);
+    if (GRAM) {
+        w_sum_partials<K>(a.gpart, 0, gU, GPART_STRIDE, KMAX * KMAX, gy1);
+        w_sum_partials<K>(a.gpart, gU, gV, GPART_STRIDE, KMAX * KMAX, gy2);
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-        const int i = e / K, j = e % K;
-        double acc = 0.0;
-        for (int l = 0; l < K; ++l) acc = fma(ru[l * K + i], tmp[l * K + j], acc);
-        a.small->Cstar[i * KMAX + j] = acc;
-    }
+    w_load<K>(a.small->RUinv, ru);
+    w_load<K>(a.small->RVinv, rv);
+    // C* = R_U^{-T} (U_f^T Y1) R_V^{-1},  C2 = R_V^{-T} (V_f^T Y2) R_U^{-1}
+    w_mm<K, false>(craw, rv, tmp);
+    w_mm<K, true>(ru, tmp, cs);
+    w_mm<K, false>(craw2, ru, tmp);
+    w_mm<K, true>(rv, tmp, c2);
+    w_store<K>(cs, a.small->Cstar);
+    w_store<K>(c2, a.small->C2);
     double rs = 0.0;
-    for (int b = threadIdx.x; b < a.n_tiles; b += blockDim.x) rs += __builtin_nontemporal_load(&a.resid[b]);
-    rs = block_sum_256(rs, red);
-    if (threadIdx.x == 0) {
+    for (int b = lane; b < a.n_tiles; b += WAVE) rs += a.resid[b];
+    for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off, WAVE);
+    int go_on = 0;
+    if (lane == 0) {
         ctrl->resid2 = rs;
         if (ctrl->stage == STAGE_SIGMA_D) ctrl->normD2 = rs;   // zeta = +inf: the residual is ||D||_F^2
         if (ctrl->stage == STAGE_MAIN) {
@@ -397,23 +563,38 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_gather(PanelArgs a) {
         ctrl->active = ctrl->done ? 0 : 1;
         ctrl->seq += 1;
         ctrl->cnt[CNT_GATHER] = 0;
+        go_on = (GRAM && a.mode == GATHER_WITH_SVD && ctrl->active) ? 1 : 0;
         publish_status(a, ctrl);
+    }
+    go_on = __shfl(go_on, 0, WAVE);
+    wave_sync();
+    if (go_on) {
+        // G1 = R_V^{-T} Gram(Y1) R_V^{-1} - C*^T C*,  G2 = R_U^{-T} Gram(Y2) R_U^{-1} - C2^T C2
+        w_mm<K, false>(gy1, rv, tmp);
+        w_mm<K, true>(rv, tmp, g1);
+        w_mm<K, false>(gy2, ru, tmp);
+        w_mm<K, true>(ru, tmp, g2);
+        w_mm<K, true>(cs, cs, craw);
+        w_mm<K, true>(c2, c2, craw2);
+        for (int e = lane; e < K * K; e += WAVE) { g1[e] -= craw[e]; g2[e] -= craw2[e]; }
+        wave_sync();
+        w_svd_tail<K>(a, ctrl, cs, c2, g1, g2, ru, rv, true);
     }
 }
 
-// ---- kernel 2: complements W1, W2, their Grams, 2K x 2K SVD, threshold ------
+// ---- kernel 2 (FP64): explicit complements W1, W2, their Grams, 2K x 2K step -
 
 template <typename T, int K>
 __global__ __launch_bounds__(PANEL_THREADS) void k_complement(PanelArgs a) {
-    constexpr int N = 2 * K;
     Ctrl* ctrl = a.ctrl;
     if (!ctrl->active) return;
     __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K];
-    __shared__ double ru[K * K], rv[K * K], cs[K * K];
+    __shared__ double ru[K * K], rv[K * K], cs[K * K], c2[K * K];
     __shared__ int flag;
-    load_small<K>(a.small->RUinv, ru);
-    load_small<K>(a.small->RVinv, rv);
-    load_small<K>(a.small->Cstar, cs);
+    block_load_small<K>(a.small->RUinv, ru);
+    block_load_small<K>(a.small->RVinv, rv);
+    block_load_small<K>(a.small->Cstar, cs);
+    block_load_small<K>(a.small->C2, c2);
     __syncthreads();
     const bool uside = (int)blockIdx.x < a.gU;
     const int row = (uside ? blockIdx.x : blockIdx.x - a.gU) * PANEL_THREADS + threadIdx.x;
@@ -437,124 +618,59 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_complement(PanelArgs a) {
         for (int t = 0; t < K; ++t) { vf[t] = static_cast<double>(Vf[(size_t)row * K + t]); y[t] = a.Y2[(size_t)row * K + t]; }
         rowmul<K>(vf, rv, vs);     // V*_j
         rowmul<K>(y, ru, ys);      // (Z^T U*)_j
-        rowmul_t<K>(vs, cs, vc);   // V*_j C*^T
+        rowmul<K>(vs, c2, vc);     // V*_j C2
 #pragma unroll
         for (int t = 0; t < K; ++t) { w[t] = ys[t] - vc[t]; a.W2[(size_t)row * K + t] = w[t]; }
     }
-    block_outer_sum<K>(w, w, sa, sb, a.gpart + (size_t)blockIdx.x * KMAX * KMAX);
+    rows_outer_sum<K, PANEL_THREADS>(w, w, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
     if (!last_block_arrives(&ctrl->cnt[CNT_COMPLEMENT], &flag)) return;
-
-    // ---- last workgroup: R1, R2, M, SVD(M), new coefficients, zeta ----
-    __shared__ double g1[K * K], g2[K * K], r1[K * K], r1i[K * K], r2[K * K], r2i[K * K];
-    __shared__ double Ma[N * N], Mv[N * N], Um[N * N], Vm[N * N], sg[N];
-    __shared__ int sweeps;
-    sum_partials<K>(a.gpart, 0, a.gU, g1);
-    sum_partials<K>(a.gpart, a.gU, a.gV, g2);
-    block_chol_inv<K>(g1, r1, r1i);
-    block_chol_inv<K>(g2, r2, r2i);
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int col = e / N, rw = e % N;
-        double v = 0.0;
-        if (rw < K && col < K) v = cs[rw * K + col];
-        else if (rw < K) v = r2[(col - K) * K + rw];          // R2^T
-        else if (col < K) v = r1[(rw - K) * K + col];         // R1
-        Ma[e] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < WAVE) {
-        const int sw = wave_jacobi_svd<N>(Ma, Mv, sg, Um, Vm);
-        if (threadIdx.x == 0) sweeps = sw;
-    }
-    __syncthreads();
-    Small* sm = a.small;
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-        const int i = e / K, j = e % K;   // coefficient row i, singular triplet j
-        double x2 = 0.0, z2 = 0.0;
-        for (int l = 0; l < K; ++l) {
-            x2 = fma(r1i[i * K + l], Um[j * N + K + l], x2);
-            z2 = fma(r2i[i * K + l], Vm[j * N + K + l], z2);
-        }
-        sm->X1[i * KMAX + j] = Um[j * N + i];
-        sm->X2[i * KMAX + j] = x2;
-        sm->Z1[i * KMAX + j] = Vm[j * N + i];
-        sm->Z2[i * KMAX + j] = z2;
-    }
-    if (threadIdx.x < N) sm->sigma_M[threadIdx.x] = sg[threadIdx.x];
-    if (threadIdx.x < K) sm->sigma_new[threadIdx.x] = sg[threadIdx.x];
-    if (threadIdx.x == 0) {
-        const int r = ctrl->r;
-        if (ctrl->stage == STAGE_MAIN) {
-            // zeta_{k+1} = beta (sigma_{r+1} + gamma^{k+1} sigma_1)  (Algorithm 1)
-            const int k = ctrl->k;
-            const double s1 = sg[0], sr1 = sg[r];
-            ctrl->sig1_pt = s1;
-            ctrl->sigr1_pt = sr1;
-            ctrl->zeta = ctrl->beta * (sr1 + pow(ctrl->gamma, (double)(k + 1)) * s1);
-            ctrl->k = k + 1;
-        } else {
-            double acc = 0.0;
-            for (int t = 0; t < r; ++t) acc += g1[t * K + t] + g2[t * K + t];
-            const double res = sg[0] > 0.0 ? sqrt(acc) / sg[0] : 0.0;
-            const double tolr = ctrl->stage == STAGE_SIGMA_D ? ctrl->tol_res_a : ctrl->tol_res_b;
-            const bool conv = res <= tolr || (ctrl->passes >= 3 && res > 0.5 * ctrl->res_prev) ||
-                              ctrl->passes >= ctrl->init_max_passes;
-            ctrl->res_prev = res;
-            if (conv && ctrl->stage == STAGE_SIGMA_D) {
-                ctrl->sigma1_D = sg[0];
-                ctrl->zeta = ctrl->beta_init * sg[0];     // zeta_{-1} = beta_init sigma_1(D)
-                ctrl->stage = STAGE_INIT_Z;
-                ctrl->passes = 0;
-                ctrl->res_prev = 1e300;
-            } else if (conv) {
-                ctrl->zeta = ctrl->beta * sg[0];          // zeta_0 = beta sigma_1(D - S_{-1})
-                ctrl->stage = STAGE_INIT_DONE;
-            }
-        }
-        ctrl->jacobi_sweeps = sweeps;
-        ctrl->cnt[CNT_COMPLEMENT] = 0;
-        publish_status(a, ctrl);
-    }
+    if (threadIdx.x >= WAVE) return;
+    __shared__ double g1[K * K], g2[K * K];
+    w_sum_partials<K>(a.gpart, 0, a.gU, GPART_STRIDE, 0, g1);
+    w_sum_partials<K>(a.gpart, a.gU, a.gV, GPART_STRIDE, 0, g2);
+    if (lane_id() == 0) ctrl->cnt[CNT_COMPLEMENT] = 0;
+    w_svd_tail<K>(a, ctrl, cs, c2, g1, g2, ru, rv, false);
 }
 
-// ---- kernel 3: new factors (or entry from a given state), Trim, Gram(A) ------
-
+// ---- kernel 3: new factors (or entry from a given state), Trim, new bases ----
+//
+// Rows: U_{k+1} = U_f E1 + S_U E2 (or a given factor), the rebuild factors of
+// L_{k+1}, Trim (Algorithm 2) and the basis for the next streaming pass,
+// U_f = dtype(Trim(U_{k+1})); the Gram of the rounded values (FP64) gives R_U.
+// Mode UPDATE_ENTER_EXACT keeps the FP64 trimmed factor and its Gram instead
+// (FP64 orthonormal bases for rpca_trim).
 template <typename T, int K>
 __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
     Ctrl* ctrl = a.ctrl;
     const bool from_m = a.mode == UPDATE_FROM_M;
     if (from_m && !ctrl->active) return;
     __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K];
-    __shared__ double ru[K * K], rv[K * K], x1[K * K], x2[K * K], sig[K];
+    __shared__ double e1[K * K], e2[K * K], sig[K];
     __shared__ int flag;
-    // Entering the loop (from a given state or from the initialisation) and
-    // updates inside the loop produce an iterate L_k: rebuild factors + Trim.
-    // Updates inside the initial subspace iteration only refresh the block.
     const bool main_stage = !from_m || ctrl->stage == STAGE_MAIN;
-    if (from_m) {
-        load_small<K>(a.small->RUinv, ru);
-        load_small<K>(a.small->RVinv, rv);
-    }
     const bool uside = (int)blockIdx.x < a.gU;
-    if (from_m) load_small<K>(uside ? a.small->X1 : a.small->Z1, x1);
-    if (from_m) load_small<K>(uside ? a.small->X2 : a.small->Z2, x2);
-    if (threadIdx.x < K) sig[threadIdx.x] = from_m ? a.small->sigma_new[threadIdx.x] : (a.src_sigma ? a.src_sigma[threadIdx.x] : 1.0);
+    if (from_m) {
+        block_load_small<K>(uside ? a.small->E1 : a.small->F1, e1);
+        block_load_small<K>(uside ? a.small->E2 : a.small->F2, e2);
+    }
+    if (threadIdx.x < K)
+        sig[threadIdx.x] = from_m ? a.small->sigma_new[threadIdx.x] : (a.src_sigma ? a.src_sigma[threadIdx.x] : 1.0);
     __syncthreads();
     const int row = (uside ? blockIdx.x : blockIdx.x - a.gU) * PANEL_THREADS + threadIdx.x;
     const int nrows = uside ? a.m : a.n;
-    double av[K];
+    double gv[K];
 #pragma unroll
-    for (int t = 0; t < K; ++t) av[t] = 0.0;
+    for (int t = 0; t < K; ++t) gv[t] = 0.0;
     if (row < nrows) {
+        T* F = tptr<T>(uside ? a.Uf : a.Vf);
         double un[K];
         if (from_m) {
-            const T* F = tptr<T>(uside ? a.Uf : a.Vf);
-            const double* Wp = uside ? a.W1 : a.W2;
-            double f[K], fs[K], w[K], p1[K], p2[K];
+            const double* S2 = uside ? a.S2U : a.S2V;
+            double f[K], s2[K], p1[K], p2[K];
 #pragma unroll
-            for (int t = 0; t < K; ++t) { f[t] = static_cast<double>(F[(size_t)row * K + t]); w[t] = Wp[(size_t)row * K + t]; }
-            rowmul<K>(f, uside ? ru : rv, fs);   // U*_i (or V*_j)
-            rowmul<K>(fs, x1, p1);
-            rowmul<K>(w, x2, p2);
+            for (int t = 0; t < K; ++t) { f[t] = static_cast<double>(F[(size_t)row * K + t]); s2[t] = S2[(size_t)row * K + t]; }
+            rowmul<K>(f, e1, p1);
+            rowmul<K>(s2, e2, p2);
 #pragma unroll
             for (int t = 0; t < K; ++t) un[t] = p1[t] + p2[t];
         } else {
@@ -583,73 +699,59 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
             const double c = sqrt(ctrl->mu * (double)K / (double)(uside ? a.m : a.n));
             if (nr > c) wgt = c / nr;
         }
-        double* Ap = uside ? a.Ap : a.Bp;
+        if (a.mode == UPDATE_ENTER_EXACT) {
+            double* Ap = uside ? a.Ap : a.Bp;
 #pragma unroll
-        for (int t = 0; t < K; ++t) { av[t] = wgt * un[t]; Ap[(size_t)row * K + t] = av[t]; }
+            for (int t = 0; t < K; ++t) { gv[t] = wgt * un[t]; Ap[(size_t)row * K + t] = gv[t]; }
+        } else {
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                const T q = static_cast<T>(wgt * un[t]);
+                F[(size_t)row * K + t] = q;
+                gv[t] = static_cast<double>(q);
+            }
+        }
     }
-    block_outer_sum<K>(av, av, sa, sb, a.gpart + (size_t)blockIdx.x * KMAX * KMAX);
+    rows_outer_sum<K, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
     if (!last_block_arrives(&ctrl->cnt[CNT_UPDATE], &flag)) return;
-
+    if (threadIdx.x >= WAVE) return;
     __shared__ double g[K * K], rr[K * K], ri[K * K];
-    sum_partials<K>(a.gpart, 0, a.gU, g);
-    block_chol_inv<K>(g, rr, ri);
-    store_small<K>(ri, a.small->RAinv);
-    __syncthreads();
-    sum_partials<K>(a.gpart, a.gU, a.gV, g);
-    block_chol_inv<K>(g, rr, ri);
-    store_small<K>(ri, a.small->RBinv);
-    if (a.sigma_dst && threadIdx.x < K) a.sigma_dst[threadIdx.x] = sig[threadIdx.x];
-    if (threadIdx.x == 0) {
+    const bool exact = a.mode == UPDATE_ENTER_EXACT;
+    w_sum_partials<K>(a.gpart, 0, a.gU, GPART_STRIDE, 0, g);
+    w_chol_inv<K>(g, rr, ri);
+    w_store<K>(ri, exact ? a.small->RAinv : a.small->RUinv);
+    w_sum_partials<K>(a.gpart, a.gU, a.gV, GPART_STRIDE, 0, g);
+    w_chol_inv<K>(g, rr, ri);
+    w_store<K>(ri, exact ? a.small->RBinv : a.small->RVinv);
+    const int lane = lane_id();
+    if (a.sigma_dst && lane < K) a.sigma_dst[lane] = sig[lane];
+    if (lane == 0) {
         if (!from_m && ctrl->stage == STAGE_INIT_DONE) ctrl->stage = STAGE_MAIN;
         ctrl->cnt[CNT_UPDATE] = 0;
     }
 }
 
-// ---- kernel 4: orthonormal bases U~ = A R_A^{-1}, their dtype copies, Grams --
+// ---- FP64 orthonormal bases U~ = A R_A^{-1} of the trimmed factors ------------
+// (rpca_trim's output; inside the loop the update kernel folds this step.)
 
 template <typename T, int K>
 __global__ __launch_bounds__(PANEL_THREADS) void k_basis(PanelArgs a) {
-    Ctrl* ctrl = a.ctrl;
-    if (a.gated && !ctrl->active) return;
-    __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K];
     __shared__ double ri[K * K];
-    __shared__ int flag;
     const bool uside = (int)blockIdx.x < a.gU;
-    load_small<K>(uside ? a.small->RAinv : a.small->RBinv, ri);
+    block_load_small<K>(uside ? a.small->RAinv : a.small->RBinv, ri);
     __syncthreads();
     const int row = (uside ? blockIdx.x : blockIdx.x - a.gU) * PANEL_THREADS + threadIdx.x;
     const int nrows = uside ? a.m : a.n;
-    double fv[K];
-#pragma unroll
-    for (int t = 0; t < K; ++t) fv[t] = 0.0;
     if (row < nrows) {
         const double* Ap = uside ? a.Ap : a.Bp;
         double av[K], q[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) av[t] = Ap[(size_t)row * K + t];
         rowmul<K>(av, ri, q);
-        T* F = tptr<T>(uside ? a.Uf : a.Vf);
         double* out = uside ? a.outU : a.outV;
 #pragma unroll
-        for (int t = 0; t < K; ++t) {
-            const T qt = static_cast<T>(q[t]);
-            F[(size_t)row * K + t] = qt;
-            fv[t] = static_cast<double>(qt);
-            if (out) out[(size_t)row * K + t] = q[t];
-        }
+        for (int t = 0; t < K; ++t) out[(size_t)row * K + t] = q[t];
     }
-    block_outer_sum<K>(fv, fv, sa, sb, a.gpart + (size_t)blockIdx.x * KMAX * KMAX);
-    if (!last_block_arrives(&ctrl->cnt[CNT_BASIS], &flag)) return;
-
-    __shared__ double g[K * K], rr[K * K], rinv[K * K];
-    sum_partials<K>(a.gpart, 0, a.gU, g);
-    block_chol_inv<K>(g, rr, rinv);
-    store_small<K>(rinv, a.small->RUinv);
-    __syncthreads();
-    sum_partials<K>(a.gpart, a.gU, a.gV, g);
-    block_chol_inv<K>(g, rr, rinv);
-    store_small<K>(rinv, a.small->RVinv);
-    if (threadIdx.x == 0) ctrl->cnt[CNT_BASIS] = 0;
 }
 
 // ---- start block of the initial subspace iteration ---------------------------
@@ -663,7 +765,7 @@ __device__ inline double hash_uniform(uint64_t seed, uint64_t idx) {
     return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-template <int K>
+template <typename T, int K>
 __global__ __launch_bounds__(PANEL_THREADS) void k_start(PanelArgs a) {
     Ctrl* ctrl = a.ctrl;
     __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K];
@@ -671,26 +773,30 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_start(PanelArgs a) {
     const bool uside = (int)blockIdx.x < a.gU;
     const int row = (uside ? blockIdx.x : blockIdx.x - a.gU) * PANEL_THREADS + threadIdx.x;
     const int nrows = uside ? a.m : a.n;
-    double av[K];
+    double gv[K];
 #pragma unroll
-    for (int t = 0; t < K; ++t) av[t] = 0.0;
+    for (int t = 0; t < K; ++t) gv[t] = 0.0;
     if (row < nrows) {
-        double* Ap = uside ? a.Ap : a.Bp;
+        T* F = tptr<T>(uside ? a.Uf : a.Vf);
         const uint64_t base = (uside ? 0ull : (uint64_t)a.m * K) + (uint64_t)row * K;
 #pragma unroll
-        for (int t = 0; t < K; ++t) { av[t] = hash_uniform(a.seed, base + t); Ap[(size_t)row * K + t] = av[t]; }
+        for (int t = 0; t < K; ++t) {
+            const T q = static_cast<T>(hash_uniform(a.seed, base + t));
+            F[(size_t)row * K + t] = q;
+            gv[t] = static_cast<double>(q);
+        }
     }
-    block_outer_sum<K>(av, av, sa, sb, a.gpart + (size_t)blockIdx.x * KMAX * KMAX);
+    rows_outer_sum<K, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
     if (!last_block_arrives(&ctrl->cnt[CNT_START], &flag)) return;
+    if (threadIdx.x >= WAVE) return;
     __shared__ double g[K * K], rr[K * K], ri[K * K];
-    sum_partials<K>(a.gpart, 0, a.gU, g);
-    block_chol_inv<K>(g, rr, ri);
-    store_small<K>(ri, a.small->RAinv);
-    __syncthreads();
-    sum_partials<K>(a.gpart, a.gU, a.gV, g);
-    block_chol_inv<K>(g, rr, ri);
-    store_small<K>(ri, a.small->RBinv);
-    if (threadIdx.x == 0) ctrl->cnt[CNT_START] = 0;
+    w_sum_partials<K>(a.gpart, 0, a.gU, GPART_STRIDE, 0, g);
+    w_chol_inv<K>(g, rr, ri);
+    w_store<K>(ri, a.small->RUinv);
+    w_sum_partials<K>(a.gpart, a.gU, a.gV, GPART_STRIDE, 0, g);
+    w_chol_inv<K>(g, rr, ri);
+    w_store<K>(ri, a.small->RVinv);
+    if (lane_id() == 0) ctrl->cnt[CNT_START] = 0;
 }
 
 __global__ void k_setup(Ctrl* ctrl, Ctrl init) { if (threadIdx.x == 0 && blockIdx.x == 0) *ctrl = init; }
@@ -717,43 +823,31 @@ __global__ void k_convert(const double* __restrict__ src, T* __restrict__ dst, i
 
 #define RPCA_LAUNCH_F(KK) hipLaunchKernelGGL((KFUN<float, KK>), grid, block, 0, s, a)
 #define RPCA_LAUNCH_D(KK) hipLaunchKernelGGL((KFUN<double, KK>), grid, block, 0, s, a)
+#define RPCA_PANEL_LAUNCHER(NAME, GRID, BLOCK)                                                   \
+    hipError_t NAME(const PanelArgs& a, int K, int dtype, hipStream_t s) {                       \
+        const dim3 grid(GRID), block(BLOCK);                                                     \
+        if (dtype == 1) { RPCA_K_SWITCH(RPCA_LAUNCH_F) } else { RPCA_K_SWITCH(RPCA_LAUNCH_D) }   \
+        return hipGetLastError();                                                                \
+    }
+
+constexpr int GATHER_RPB = GATHER_THREADS / GATHER_SPLIT;
 
 #define KFUN k_gather
-hipError_t launch_gather(const PanelArgs& a, int K, int dtype, hipStream_t s) {
-    constexpr int RPB = PANEL_THREADS / GATHER_SPLIT;
-    const dim3 grid((unsigned)((a.m + RPB - 1) / RPB + (a.n + RPB - 1) / RPB)), block(PANEL_THREADS);
-    if (dtype == 1) { RPCA_K_SWITCH(RPCA_LAUNCH_F) } else { RPCA_K_SWITCH(RPCA_LAUNCH_D) }
-    return hipGetLastError();
-}
+RPCA_PANEL_LAUNCHER(launch_gather, (unsigned)((a.m + GATHER_RPB - 1) / GATHER_RPB + (a.n + GATHER_RPB - 1) / GATHER_RPB),
+                    GATHER_THREADS)
 #undef KFUN
 #define KFUN k_complement
-hipError_t launch_complement(const PanelArgs& a, int K, int dtype, hipStream_t s) {
-    const dim3 grid((unsigned)(a.gU + a.gV)), block(PANEL_THREADS);
-    if (dtype == 1) { RPCA_K_SWITCH(RPCA_LAUNCH_F) } else { RPCA_K_SWITCH(RPCA_LAUNCH_D) }
-    return hipGetLastError();
-}
+RPCA_PANEL_LAUNCHER(launch_complement, (unsigned)(a.gU + a.gV), PANEL_THREADS)
 #undef KFUN
 #define KFUN k_update
-hipError_t launch_update(const PanelArgs& a, int K, int dtype, hipStream_t s) {
-    const dim3 grid((unsigned)(a.gU + a.gV)), block(PANEL_THREADS);
-    if (dtype == 1) { RPCA_K_SWITCH(RPCA_LAUNCH_F) } else { RPCA_K_SWITCH(RPCA_LAUNCH_D) }
-    return hipGetLastError();
-}
+RPCA_PANEL_LAUNCHER(launch_update, (unsigned)(a.gU + a.gV), PANEL_THREADS)
 #undef KFUN
 #define KFUN k_basis
-hipError_t launch_basis(const PanelArgs& a, int K, int dtype, hipStream_t s) {
-    const dim3 grid((unsigned)(a.gU + a.gV)), block(PANEL_THREADS);
-    if (dtype == 1) { RPCA_K_SWITCH(RPCA_LAUNCH_F) } else { RPCA_K_SWITCH(RPCA_LAUNCH_D) }
-    return hipGetLastError();
-}
+RPCA_PANEL_LAUNCHER(launch_basis, (unsigned)(a.gU + a.gV), PANEL_THREADS)
 #undef KFUN
-
-#define RPCA_LAUNCH_START(KK) hipLaunchKernelGGL((k_start<KK>), grid, block, 0, s, a)
-hipError_t launch_start(const PanelArgs& a, int K, hipStream_t s) {
-    const dim3 grid((unsigned)(a.gU + a.gV)), block(PANEL_THREADS);
-    RPCA_K_SWITCH(RPCA_LAUNCH_START)
-    return hipGetLastError();
-}
+#define KFUN k_start
+RPCA_PANEL_LAUNCHER(launch_start, (unsigned)(a.gU + a.gV), PANEL_THREADS)
+#undef KFUN
 
 hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, hipStream_t s) {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, s, ctrl, init);

@@ -56,7 +56,8 @@ class State(ctypes.Structure):
     _fields_ = [("U", ctypes.c_void_p), ("V", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
                 ("zeta", ctypes.c_double), ("err", ctypes.c_double),
                 ("sigma1_pt", ctypes.c_double), ("sigma_r1_pt", ctypes.c_double),
-                ("normD", ctypes.c_double), ("k", ctypes.c_int32), ("init_passes", ctypes.c_int32)]
+                ("normD", ctypes.c_double), ("k", ctypes.c_int32), ("init_passes", ctypes.c_int32),
+                ("svd_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _LIB = None
@@ -193,6 +194,7 @@ class SolveInfo:
     err_hist: list
     zeta_hist: list
     init_passes: int
+    svd_sweeps: int
 
 
 def make_params(D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: float, mu: float,
@@ -271,7 +273,7 @@ class Solver:
         k = self.state.k
         return SolveInfo(status=st, iterations=k, err=self.state.err, zeta=self.state.zeta,
                          err_hist=list(eh[:k + 1]), zeta_hist=list(zh[:k + 1]),
-                         init_passes=self.state.init_passes)
+                         init_passes=self.state.init_passes, svd_sweeps=self.state.svd_sweeps)
 
     def materialize(self, want_L: bool = True, want_S: bool = True):
         L = torch.empty_like(self.D) if want_L else None

@@ -35,7 +35,7 @@ def test_struct_layout_matches_header(lib):
     # offsets the C compiler uses for the two structs (natural alignment)
     assert ctypes.sizeof(R.Params) == 8 * 3 + 4 * 2 + 8 * 5 + 4 * 4 + 8
     assert R.Params.seed.offset == ctypes.sizeof(R.Params) - 8
-    assert ctypes.sizeof(R.State) == 8 * 3 + 8 * 5 + 4 * 2
+    assert ctypes.sizeof(R.State) == 8 * 3 + 8 * 5 + 4 * 4
 
 
 def _params(**kw):
