@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4])
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--init-block", type=int, default=0, help="block width of the initialisation (0: library default)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -96,7 +97,8 @@ def main():
     dev = torch.device("cuda:0")
     D = torch.as_tensor(x.D, dtype=torch.float32, device=dev)
     m, n = x.m, x.n
-    sv = R.Solver(D, x.r, x.beta, x.beta_init, x.gamma, x.mu_in, tol=x.tol, max_iter=100, seed=1)
+    sv = R.Solver(D, x.r, x.beta, x.beta_init, x.gamma, x.mu_in, tol=x.tol, max_iter=100, seed=1,
+                  init_block=args.init_block)
 
     for i in range(args.warmup):
         info = sv.solve()

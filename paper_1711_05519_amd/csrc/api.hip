@@ -149,7 +149,7 @@ void prof_drop_last() {
 
 int init_block_of(const rpca_params* p) {
     if (p->init_block > 0) return p->init_block;
-    int q = p->r + 4;
+    int q = p->r + 2;
     if (q > KMAX) q = KMAX;
     const int64_t lim = (p->m < p->n ? p->m : p->n) / 2;
     if (q > lim) q = (int)lim;
@@ -222,7 +222,8 @@ Layout make_layout(const rpca_params* p) {
     L.off_hist = take(2 * sizeof(double) * (size_t)(p->max_iter + 1));
     L.off_P1 = take((size_t)L.n_ct * m * L.KW * L.acc);
     L.off_P2 = take((size_t)L.n_rt_max * n * L.KW * L.acc);
-    L.off_resid = take(sizeof(double) * (size_t)L.n_ct * L.n_rt_max);
+    // per-tile residual sums, then (init passes) per-tile max |D_ij|
+    L.off_resid = take(2 * sizeof(double) * (size_t)L.n_ct * L.n_rt_max);
     L.off_gpart = take(sizeof(double) * (size_t)(g_gather > L.gU + L.gV ? g_gather : L.gU + L.gV) * GPART_STRIDE);
     const size_t pm = sizeof(double) * (size_t)m * L.KW, pn = sizeof(double) * (size_t)n * L.KW;
     L.off_Y1 = take(pm); L.off_Y2 = take(pn);
@@ -291,6 +292,7 @@ Ctrl base_ctrl(const Ctx& c, int stage, double zeta, int k, double normD2, int w
     t.tol_res_b = p->dtype == RPCA_F64 ? 1e-13 : 3e-6;
     // rounding level of the streamed products relative to sigma_1
     t.sigma_dead = p->dtype == RPCA_F64 ? 1e-12 : 1e-5;
+    t.single = p->dtype == RPCA_F32 ? 1 : 0;
     return t;
 }
 

@@ -78,6 +78,9 @@ struct Ctrl {
     double tol_res_a, tol_res_b;
     double resid2;       // last residual sum (sum over |x| <= zeta of x^2)
     double sigma_dead;   // relative size below which a singular triplet of M is dropped
+    double max_abs_D;    // max |D_ij| (from the init passes, where L = 0)
+    int32_t single;      // 1: D and the streamed factors are FP32
+    int32_t pad_;
 };
 
 // Small FP64 matrices shared between kernels (all K x K, row-major, ld = KMAX).
@@ -127,20 +130,25 @@ __device__ inline bool body_runs(const Ctrl* c, int body) {
     return true;
 }
 
-// Signals completion of this workgroup's partial results; returns true in the
-// single workgroup that finished last. Partials written before the call are
-// visible to that workgroup afterwards. The counter is reset by the caller.
+// Signals completion of this workgroup's partial results; returns true in all
+// threads of the single workgroup that finished last. Partials written by any
+// thread of any workgroup before the call are visible to that workgroup
+// afterwards. The counter is reset by the caller.
+// Thread 0 alone issues the agent-scope fences, after a workgroup barrier
+// (which completes every wave's stores at workgroup scope; the release fence
+// is cumulative over them) and before the barrier that hands the result to the
+// other waves. A fence in every wave multiplies the L2 write-backs.
 __device__ inline bool last_block_arrives(uint32_t* counter, int* flag_smem) {
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t prev = atomicAdd(counter, 1u);
-        *flag_smem = (prev == gridDim.x - 1) ? 1 : 0;
+        __threadfence();
+        const uint32_t prev = atomicAdd(counter, 1u);
+        const int last = (prev == gridDim.x - 1) ? 1 : 0;
+        if (last) __threadfence();
+        *flag_smem = last;
     }
     __syncthreads();
-    const bool last = *flag_smem != 0;
-    if (last) __threadfence();
-    return last;
+    return *flag_smem != 0;
 }
 
 }  // namespace rpca

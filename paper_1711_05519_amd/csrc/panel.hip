@@ -114,49 +114,85 @@ __device__ inline void w_mm(const double* A, const double* B, double* C) {
     wave_sync();
 }
 
-// Fixed-order sum of partial blocks b in [first, first+count) of gpart (block b
-// at gpart + b*stride + off) into s (LDS, K*K entries). The wave first copies
-// a chunk of blocks to LDS with all its loads in flight at once (the caches
-// were just invalidated by the acquire fence, so every load goes to memory),
-// then lane e adds entry e of the chunk's blocks in block order.
-template <int K>
-__device__ void w_sum_partials(const double* gpart, int first, int count, int stride, int off, double* s) {
-    constexpr int E = K * K;
-    constexpr int PER_LANE = 16;
-    constexpr int CH = (WAVE * PER_LANE) / E;   // blocks per chunk
-    __shared__ double stage[CH * E];
-    const int lane = lane_id();
-    double run[(E + WAVE - 1) / WAVE];
+// One sum of per-workgroup partials: dst[e] = sum over b < count of
+// gpart[(first + b) * GPART_STRIDE + off + e], e < E.
+struct SumJob {
+    int first, count, off;
+    double* dst;
+};
+
+template <int J>
+__device__ inline SumJob pick_job(const SumJob (&jobs)[J], int j) {
+    SumJob r = jobs[0];
 #pragma unroll
-    for (int u = 0; u < (E + WAVE - 1) / WAVE; ++u) run[u] = 0.0;
-    for (int b0 = 0; b0 < count; b0 += CH) {
-        const int nb = count - b0 < CH ? count - b0 : CH;
-        double v[PER_LANE];
-#pragma unroll
-        for (int u = 0; u < PER_LANE; ++u) {
-            const int i = lane + WAVE * u;         // i = block * E + entry within the chunk
-            v[u] = i < nb * E ? gpart[(size_t)(first + b0 + i / E) * stride + off + (i % E)] : 0.0;
+    for (int i = 1; i < J; ++i)
+        if (j == i) r = jobs[i];
+    return r;
+}
+
+// The whole workgroup (NT threads) sums J jobs of E entries. Thread t takes
+// pair q = t % PAIRS (job q / E, entry q % E) and split s = t / PAIRS and sums
+// the partials b = s, s + S, ... in order; the S split sums of a pair are then
+// added in order of s. All loads of a round are independent, so a round costs
+// one memory latency. part: NT doubles of LDS.
+template <int E, int J, int NT>
+__device__ void block_sum_partials(const double* __restrict__ gpart, const SumJob (&jobs)[J], double* part) {
+    constexpr int PAIRS = J * E;
+    constexpr int PR = PAIRS >= NT ? NT : PAIRS;   // pairs per round
+    constexpr int S = NT / PR;                     // splits per pair
+    const int t = threadIdx.x;
+    for (int q0 = 0; q0 < PAIRS; q0 += PR) {
+        const int sp = t / PR, q = q0 + t % PR;
+        double acc = 0.0;
+        if (sp < S && q < PAIRS) {
+            const SumJob jb = pick_job<J>(jobs, q / E);
+            const double* g = gpart + (size_t)jb.first * GPART_STRIDE + jb.off + (q % E);
+#pragma unroll 4
+            for (int b = sp; b < jb.count; b += S) acc += g[(size_t)b * GPART_STRIDE];
         }
-#pragma unroll
-        for (int u = 0; u < PER_LANE; ++u) {
-            const int i = lane + WAVE * u;
-            if (i < nb * E) stage[i] = v[u];
+        if (t < S * PR) part[t] = acc;
+        __syncthreads();
+        if (t < PR && q0 + t < PAIRS) {
+            double v = 0.0;
+            for (int u = 0; u < S; ++u) v += part[u * PR + t];
+            pick_job<J>(jobs, (q0 + t) / E).dst[(q0 + t) % E] = v;
         }
-        wave_sync();
-#pragma unroll
-        for (int u = 0; u < (E + WAVE - 1) / WAVE; ++u) {
-            const int e = lane + WAVE * u;
-            if (e < E)
-                for (int b = 0; b < nb; ++b) run[u] += stage[b * E + e];
-        }
-        wave_sync();
+        __syncthreads();
     }
-#pragma unroll
-    for (int u = 0; u < (E + WAVE - 1) / WAVE; ++u) {
-        const int e = lane + WAVE * u;
-        if (e < E) s[e] = run[u];
+}
+
+// Sum of the per-tile residuals (and, if want_max, the max of the per-tile
+// max |D_ij| stored after them) by the whole workgroup, in a fixed order.
+// out[0] = sum, out[1] = max. part: at least 2 * NT / WAVE doubles of LDS.
+template <int NT>
+__device__ void block_resid(const double* __restrict__ resid, int n_tiles, bool want_max, double* part,
+                            double* out) {
+    const int t = threadIdx.x;
+    double sm = 0.0, mx = 0.0;
+    for (int b = t; b < n_tiles; b += NT) {
+        sm += resid[b];
+        if (want_max) mx = fmax(mx, resid[n_tiles + b]);
     }
-    wave_sync();
+    for (int off = 32; off > 0; off >>= 1) {
+        sm += __shfl_xor(sm, off, WAVE);
+        mx = fmax(mx, __shfl_xor(mx, off, WAVE));
+    }
+    constexpr int NW = NT / WAVE;
+    if ((t & (WAVE - 1)) == 0) {
+        part[t / WAVE] = sm;
+        part[NW + t / WAVE] = mx;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double a = 0.0, m = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            a += part[w];
+            m = fmax(m, part[NW + w]);
+        }
+        out[0] = a;
+        out[1] = m;
+    }
+    __syncthreads();
 }
 
 // G = R^T R with R upper triangular (LDS, ld K) and Rinv = R^{-1}; lane c
@@ -429,17 +465,33 @@ __device__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, con
             double acc = 0.0;
             for (int t = 0; t < r; ++t) acc += fmax(g1[t * K + t], 0.0) + fmax(g2[t * K + t], 0.0);
             const double res = sg[0] > 0.0 ? sqrt(acc) / sg[0] : 0.0;
-            const double tolr = ctrl->stage == STAGE_SIGMA_D ? ctrl->tol_res_a : ctrl->tol_res_b;
-            const bool conv = res <= tolr || (ctrl->passes >= 3 && res > 0.5 * ctrl->res_prev) ||
-                              ctrl->passes >= ctrl->init_max_passes;
+            // Converged: below the stage's tolerance; or stalled (less than a
+            // halving per pass) within 100x of it, where rounding of the
+            // products limits the residual; or at the pass cap.
+            const bool stall = ctrl->passes >= 3 && res > 0.5 * ctrl->res_prev;
+            const bool capped = ctrl->passes >= ctrl->init_max_passes;
+            const bool conv_a = res <= ctrl->tol_res_a || (stall && res <= 100.0 * ctrl->tol_res_a) || capped;
+            const bool conv_b = res <= ctrl->tol_res_b || (stall && res <= 100.0 * ctrl->tol_res_b) || capped;
+            const double res_last = res;
             ctrl->res_prev = res;
-            if (conv && ctrl->stage == STAGE_SIGMA_D) {
+            if (ctrl->stage == STAGE_SIGMA_D && conv_a) {
                 ctrl->sigma1_D = sg[0];
-                ctrl->zeta = ctrl->beta_init * sg[0];     // zeta_{-1} = beta_init sigma_1(D)
-                ctrl->stage = STAGE_INIT_Z;
-                ctrl->passes = 0;
-                ctrl->res_prev = 1e300;
-            } else if (conv) {
+                const double z1 = ctrl->beta_init * sg[0];   // zeta_{-1} = beta_init sigma_1(D)
+                ctrl->zeta = z1;
+                // The stream passes compare |D_ij| > zeta in the precision of D.
+                // When no entry exceeds zeta_{-1} there, S_{-1} is empty and
+                // D - S_{-1} = D: the block already iterates on that matrix.
+                const double zt = ctrl->single ? (double)(float)z1 : z1;
+                const bool s_empty = ctrl->max_abs_D <= zt;
+                if (s_empty && conv_b) {
+                    ctrl->zeta = ctrl->beta * sg[0];      // zeta_0 = beta sigma_1(D - S_{-1})
+                    ctrl->stage = STAGE_INIT_DONE;
+                } else {
+                    ctrl->stage = STAGE_INIT_Z;
+                    ctrl->passes = 0;
+                    ctrl->res_prev = s_empty ? res_last : 1e300;
+                }
+            } else if (ctrl->stage == STAGE_INIT_Z && conv_b) {
                 ctrl->zeta = ctrl->beta * sg[0];          // zeta_0 = beta sigma_1(D - S_{-1})
                 ctrl->stage = STAGE_INIT_DONE;
             }
@@ -519,18 +571,23 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     if (GRAM) rows_outer_sum<K, RPB>(y, y, writer, slot, sa, sb, gp + KMAX * KMAX);
     if (!last_block_arrives(&ctrl->cnt[CNT_GATHER], &flag)) return;
 
-    // ---- last workgroup: one wave from here on ----
-    if (threadIdx.x >= WAVE) return;
+    // ---- last workgroup: all threads sum the partials, then one wave ----
     __shared__ double craw[K * K], craw2[K * K], ru[K * K], rv[K * K], cs[K * K], c2[K * K], tmp[K * K];
     __shared__ double gy1[K * K], gy2[K * K], g1[K * K], g2[K * K];
-    const int lane = lane_id();
+    __shared__ double part[GATHER_THREADS], rsum[2];
     const int gV = gridDim.x - gU;
-    w_sum_partials<K>(a.gpart, 0, gU, GPART_STRIDE, 0, craw);
-    w_sum_partials<K>(a.gpart, gU, gV, GPART_STRIDE, 0, craw2);
+    const bool sigma_stage = ctrl->stage == STAGE_SIGMA_D;
+    block_resid<GATHER_THREADS>(a.resid, a.n_tiles, sigma_stage, part, rsum);
     if (GRAM) {
-        w_sum_partials<K>(a.gpart, 0, gU, GPART_STRIDE, KMAX * KMAX, gy1);
-        w_sum_partials<K>(a.gpart, gU, gV, GPART_STRIDE, KMAX * KMAX, gy2);
+        const SumJob jobs[4] = {{0, gU, 0, craw}, {gU, gV, 0, craw2}, {0, gU, KMAX * KMAX, gy1},
+                                {gU, gV, KMAX * KMAX, gy2}};
+        block_sum_partials<K * K, 4, GATHER_THREADS>(a.gpart, jobs, part);
+    } else {
+        const SumJob jobs[2] = {{0, gU, 0, craw}, {gU, gV, 0, craw2}};
+        block_sum_partials<K * K, 2, GATHER_THREADS>(a.gpart, jobs, part);
     }
+    if (threadIdx.x >= WAVE) return;
+    const int lane = lane_id();
     w_load<K>(a.small->RUinv, ru);
     w_load<K>(a.small->RVinv, rv);
     // C* = R_U^{-T} (U_f^T Y1) R_V^{-1},  C2 = R_V^{-T} (V_f^T Y2) R_U^{-1}
@@ -540,13 +597,14 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     w_mm<K, true>(rv, tmp, c2);
     w_store<K>(cs, a.small->Cstar);
     w_store<K>(c2, a.small->C2);
-    double rs = 0.0;
-    for (int b = lane; b < a.n_tiles; b += WAVE) rs += a.resid[b];
-    for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off, WAVE);
+    const double rs = rsum[0], mx = rsum[1];
     int go_on = 0;
     if (lane == 0) {
         ctrl->resid2 = rs;
-        if (ctrl->stage == STAGE_SIGMA_D) ctrl->normD2 = rs;   // zeta = +inf: the residual is ||D||_F^2
+        if (sigma_stage) {
+            ctrl->normD2 = rs;   // zeta = +inf: the residual is ||D||_F^2
+            ctrl->max_abs_D = mx;
+        }
         if (ctrl->stage == STAGE_MAIN) {
             const double err = sqrt(rs / ctrl->normD2);
             ctrl->err = err;
@@ -624,10 +682,12 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_complement(PanelArgs a) {
     }
     rows_outer_sum<K, PANEL_THREADS>(w, w, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
     if (!last_block_arrives(&ctrl->cnt[CNT_COMPLEMENT], &flag)) return;
+    __shared__ double g1[K * K], g2[K * K], part[PANEL_THREADS];
+    {
+        const SumJob jobs[2] = {{0, a.gU, 0, g1}, {a.gU, a.gV, 0, g2}};
+        block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, jobs, part);
+    }
     if (threadIdx.x >= WAVE) return;
-    __shared__ double g1[K * K], g2[K * K];
-    w_sum_partials<K>(a.gpart, 0, a.gU, GPART_STRIDE, 0, g1);
-    w_sum_partials<K>(a.gpart, a.gU, a.gV, GPART_STRIDE, 0, g2);
     if (lane_id() == 0) ctrl->cnt[CNT_COMPLEMENT] = 0;
     w_svd_tail<K>(a, ctrl, cs, c2, g1, g2, ru, rv, false);
 }
@@ -714,14 +774,16 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
     }
     rows_outer_sum<K, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
     if (!last_block_arrives(&ctrl->cnt[CNT_UPDATE], &flag)) return;
+    __shared__ double g[K * K], gb[K * K], rr[K * K], ri[K * K], part[PANEL_THREADS];
+    {
+        const SumJob jobs[2] = {{0, a.gU, 0, g}, {a.gU, a.gV, 0, gb}};
+        block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, jobs, part);
+    }
     if (threadIdx.x >= WAVE) return;
-    __shared__ double g[K * K], rr[K * K], ri[K * K];
     const bool exact = a.mode == UPDATE_ENTER_EXACT;
-    w_sum_partials<K>(a.gpart, 0, a.gU, GPART_STRIDE, 0, g);
     w_chol_inv<K>(g, rr, ri);
     w_store<K>(ri, exact ? a.small->RAinv : a.small->RUinv);
-    w_sum_partials<K>(a.gpart, a.gU, a.gV, GPART_STRIDE, 0, g);
-    w_chol_inv<K>(g, rr, ri);
+    w_chol_inv<K>(gb, rr, ri);
     w_store<K>(ri, exact ? a.small->RBinv : a.small->RVinv);
     const int lane = lane_id();
     if (a.sigma_dst && lane < K) a.sigma_dst[lane] = sig[lane];
@@ -788,13 +850,15 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_start(PanelArgs a) {
     }
     rows_outer_sum<K, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
     if (!last_block_arrives(&ctrl->cnt[CNT_START], &flag)) return;
+    __shared__ double g[K * K], gb[K * K], rr[K * K], ri[K * K], part[PANEL_THREADS];
+    {
+        const SumJob jobs[2] = {{0, a.gU, 0, g}, {a.gU, a.gV, 0, gb}};
+        block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, jobs, part);
+    }
     if (threadIdx.x >= WAVE) return;
-    __shared__ double g[K * K], rr[K * K], ri[K * K];
-    w_sum_partials<K>(a.gpart, 0, a.gU, GPART_STRIDE, 0, g);
     w_chol_inv<K>(g, rr, ri);
     w_store<K>(ri, a.small->RUinv);
-    w_sum_partials<K>(a.gpart, a.gU, a.gV, GPART_STRIDE, 0, g);
-    w_chol_inv<K>(g, rr, ri);
+    w_chol_inv<K>(gb, rr, ri);
     w_store<K>(ri, a.small->RVinv);
     if (lane_id() == 0) ctrl->cnt[CNT_START] = 0;
 }

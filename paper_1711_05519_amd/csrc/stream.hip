@@ -188,7 +188,7 @@ template <typename T, int K, bool REBUILD, bool CHECK>
 __device__ __forceinline__ void compute_batch(
     const T (&d)[StreamCfg<T, K>::NB][STREAM_CPL], const T* __restrict__ AL, const T* __restrict__ Uf,
     int i0, int i_hi, T zeta, const T (&bl)[STREAM_CPL][K], const T (&vt)[STREAM_CPL][K],
-    T (&y2)[STREAM_CPL][K], double& res, typename AccOf<T>::type* __restrict__ P1t, int lane) {
+    T (&y2)[STREAM_CPL][K], double& res, T& amax, typename AccOf<T>::type* __restrict__ P1t, int lane) {
     using Acc = typename AccOf<T>::type;
     constexpr int NB = StreamCfg<T, K>::NB;
     T p[NB * K];
@@ -213,6 +213,7 @@ __device__ __forceinline__ void compute_batch(
 #pragma unroll
                     for (int t = 0; t < K; ++t) x = fma(-al[t], bl[s][t], x);
                 }
+                if constexpr (!REBUILD) amax = fmax(amax, fabs(x));   // L = 0: x = D_ij
                 const bool big = fabs(x) > zeta;   // S_ij = x  (T_zeta keeps |x| > zeta)
                 const T e = big ? T(0) : x;        // entry of D - L - S
                 rs = fma(e, e, rs);
@@ -241,7 +242,7 @@ template <typename T, int K, bool REBUILD, bool FULL>
 __device__ __forceinline__ void stream_rows(
     const T* __restrict__ D, int64_t ldd, const T* __restrict__ AL, const T* __restrict__ Uf,
     int i_first, int i_hi, int jb, int nvalid, T zeta, const T (&bl)[STREAM_CPL][K],
-    const T (&vt)[STREAM_CPL][K], T (&y2)[STREAM_CPL][K], double& res,
+    const T (&vt)[STREAM_CPL][K], T (&y2)[STREAM_CPL][K], double& res, T& amax,
     typename AccOf<T>::type* __restrict__ P1t, int lane) {
     constexpr int NB = StreamCfg<T, K>::NB;
     constexpr int STEP = STREAM_WAVES * NB;
@@ -258,7 +259,7 @@ __device__ __forceinline__ void stream_rows(
                 const int i1 = i0 + STEP;
                 const bool more = i1 + STREAM_WAVES * (NB - 1) < i_hi;
                 if (more) load_batch<T, K, true, false>(D, ldd, i1, i_hi, jb, nvalid, nxt);
-                compute_batch<T, K, REBUILD, false>(cur, AL, Uf, i0, i_hi, zeta, bl, vt, y2, res, P1t, lane);
+                compute_batch<T, K, REBUILD, false>(cur, AL, Uf, i0, i_hi, zeta, bl, vt, y2, res, amax, P1t, lane);
                 i0 = i1;
                 if (!more) break;
             }
@@ -267,7 +268,7 @@ __device__ __forceinline__ void stream_rows(
     for (; i0 < i_hi; i0 += STEP) {
         T cur[NB][STREAM_CPL];
         load_batch<T, K, FULL, true>(D, ldd, i0, i_hi, jb, nvalid, cur);
-        compute_batch<T, K, REBUILD, true>(cur, AL, Uf, i0, i_hi, zeta, bl, vt, y2, res, P1t, lane);
+        compute_batch<T, K, REBUILD, true>(cur, AL, Uf, i0, i_hi, zeta, bl, vt, y2, res, amax, P1t, lane);
     }
 }
 
@@ -302,14 +303,15 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream(
     const int i_lo = rt * g.TM;
     const int i_hi = min(g.m, i_lo + g.TM);
     double res = 0.0;
+    T amax = T(0);
     Acc* P1t = P1 + (size_t)ct * g.m * K;
     const bool full = g.vec_ok && (ct + 1) * STREAM_TN <= g.n;   // uniform per workgroup
     if (full)
         stream_rows<T, K, REBUILD, true>(D, g.ldd, AL, Uf, i_lo + wave, i_hi, jb, nvalid, zeta, bl, vt, y2, res,
-                                         P1t, lane);
+                                         amax, P1t, lane);
     else
         stream_rows<T, K, REBUILD, false>(D, g.ldd, AL, Uf, i_lo + wave, i_hi, jb, nvalid, zeta, bl, vt, y2, res,
-                                          P1t, lane);
+                                          amax, P1t, lane);
 
     // Y2 partial: sum the four waves' column partials through LDS.
     __shared__ Acc sm[STREAM_TN * K];
@@ -332,6 +334,18 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream(
     }
     const double rtot = block_sum_256(res, red);
     if (threadIdx.x == 0) resid[blockIdx.x] = rtot;
+    if constexpr (!REBUILD) {
+        // max |D_ij| over the tile, behind the residuals of all tiles
+        double v = static_cast<double>(amax);
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, WAVE));
+        if (lane == 0) red[wave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double mx = red[0];
+            for (int w = 1; w < STREAM_WAVES; ++w) mx = fmax(mx, red[w]);
+            resid[gridDim.x + blockIdx.x] = mx;
+        }
+    }
 }
 
 // Dense L = AL BL^T and S = T_zeta(D - L) (outputs of Algorithm 1).
