@@ -158,11 +158,13 @@ __device__ inline void load4(const double* __restrict__ p, int nvalid, bool vec,
 
 template <typename T, int K> struct StreamCfg {
     // Rows per batch per wave. The batch's wave-uniform row data (2K values of
-    // AL and Uf per row) live in scalar registers; about 60 SGPRs of them fit
-    // without spilling. The per-element cost of the reduce-scatter depends on
-    // NB * K only weakly, so smaller batches cost little.
+    // AL and Uf per row) live in scalar registers. The per-element cost of the
+    // reduce-scatter depends on NB * K only weakly, so smaller batches cost
+    // little, while the registers of the two batches in flight set the
+    // occupancy: NB * K ~ 16 keeps K = 5 at 127 VGPRs (4 waves per SIMD),
+    // measured 25% faster than NB * K ~ 32 (2 waves per SIMD).
     static constexpr int WORDS = (int)(sizeof(T) / 4);
-    static constexpr int NB0 = 32 / (K * WORDS);
+    static constexpr int NB0 = 16 / (K * WORDS);
     static constexpr int NB = NB0 < 1 ? 1 : (NB0 > 8 ? 8 : NB0);
 };
 
