@@ -14,7 +14,7 @@ constexpr int STREAM_WAVES = STREAM_THREADS / WAVE;
 constexpr int STREAM_CPL = 4;     // consecutive columns owned by one lane
 constexpr int STREAM_TN = WAVE * STREAM_CPL;   // columns per stream tile
 constexpr int PANEL_THREADS = 256;
-constexpr int GATHER_SPLIT = 4;   // adjacent lanes sharing one row in the gather kernel
+constexpr int GATHER_SPLIT = 8;   // adjacent lanes sharing one row in the gather kernel (<= 16)
 constexpr int GATHER_THREADS = 1024;
 constexpr int GPART_STRIDE = 2 * KMAX * KMAX;   // doubles per workgroup partial slot
 

@@ -114,48 +114,47 @@ __device__ inline void w_mm(const double* A, const double* B, double* C) {
     wave_sync();
 }
 
-// One sum of per-workgroup partials: dst[e] = sum over b < count of
-// gpart[(first + b) * GPART_STRIDE + off + e], e < E.
-struct SumJob {
-    int first, count, off;
-    double* dst;
-};
-
-template <int J>
-__device__ inline SumJob pick_job(const SumJob (&jobs)[J], int j) {
-    SumJob r = jobs[0];
-#pragma unroll
-    for (int i = 1; i < J; ++i)
-        if (j == i) r = jobs[i];
-    return r;
-}
-
-// The whole workgroup (NT threads) sums J jobs of E entries. Thread t takes
-// pair q = t % PAIRS (job q / E, entry q % E) and split s = t / PAIRS and sums
-// the partials b = s, s + S, ... in order; the S split sums of a pair are then
-// added in order of s. All loads of a round are independent, so a round costs
-// one memory latency. part: NT doubles of LDS.
+// Sums of the per-workgroup partials of a kernel whose first gU workgroups
+// cover the U side (rows of m) and the next gV the V side (rows of n). Job j
+// sums entry e < E of the partial at offset (j / 2) * KMAX^2 of every
+// workgroup of side j % 2, into out[j * E + e].
+// The whole workgroup (NT threads) takes part. Thread t takes pair
+// q = t % PAIRS (job q / E, entry q % E) and split s = t / PAIRS and sums the
+// partials b = s, s + S, ... in order; the S split sums of a pair are then
+// added in order of s. Up to 16 loads per thread are in flight at once, so a
+// round over up to 16 S partials costs one memory latency. part: NT doubles
+// of LDS.
 template <int E, int J, int NT>
-__device__ void block_sum_partials(const double* __restrict__ gpart, const SumJob (&jobs)[J], double* part) {
+__device__ void block_sum_partials(const double* __restrict__ gpart, int gU, int gV, double* out, double* part) {
     constexpr int PAIRS = J * E;
     constexpr int PR = PAIRS >= NT ? NT : PAIRS;   // pairs per round
     constexpr int S = NT / PR;                     // splits per pair
+    constexpr int L = 16;                          // loads in flight per thread
     const int t = threadIdx.x;
     for (int q0 = 0; q0 < PAIRS; q0 += PR) {
         const int sp = t / PR, q = q0 + t % PR;
         double acc = 0.0;
         if (sp < S && q < PAIRS) {
-            const SumJob jb = pick_job<J>(jobs, q / E);
-            const double* g = gpart + (size_t)jb.first * GPART_STRIDE + jb.off + (q % E);
-#pragma unroll 4
-            for (int b = sp; b < jb.count; b += S) acc += g[(size_t)b * GPART_STRIDE];
+            const int j = q / E, e = q - (q / E) * E;
+            const int first = (j & 1) ? gU : 0, count = (j & 1) ? gV : gU;
+            const double* g = gpart + (size_t)first * GPART_STRIDE + (j >> 1) * (KMAX * KMAX) + e;
+            for (int b0 = sp; b0 < count; b0 += L * S) {
+                double v[L];
+#pragma unroll
+                for (int u = 0; u < L; ++u) {
+                    const int b = b0 + u * S;
+                    v[u] = b < count ? g[(size_t)b * GPART_STRIDE] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < L; ++u) acc += v[u];
+            }
         }
         if (t < S * PR) part[t] = acc;
         __syncthreads();
         if (t < PR && q0 + t < PAIRS) {
             double v = 0.0;
             for (int u = 0; u < S; ++u) v += part[u * PR + t];
-            pick_job<J>(jobs, (q0 + t) / E).dst[(q0 + t) % E] = v;
+            out[q0 + t] = v;
         }
         __syncthreads();
     }
@@ -195,47 +194,64 @@ __device__ void block_resid(const double* __restrict__ resid, int n_tiles, bool 
     __syncthreads();
 }
 
-// G = R^T R with R upper triangular (LDS, ld K) and Rinv = R^{-1}; lane c
-// owns column c. A pivot that vanishes (d <= CHOL_DEAD_REL * G_jj or G_jj ~ 0)
-// marks a numerically dependent column: its row of R and column of Rinv are 0.
+__device__ inline double readlane64(double x, int l) {
+    const int64_t u = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Two Cholesky factorisations at once, G0 = R0^T R0 in lanes 0..31 and
+// G1 = R1^T R1 in lanes 32..63, with the inverses R^{-1} (all K x K, ld K,
+// LDS; R upper triangular). Lane c of a half owns column c in registers; the
+// factorisation is right-looking: at step j the pivot and row j of R are
+// formed in registers and broadcast with readlane, and the trailing columns
+// are updated. A pivot that vanishes (d <= CHOL_DEAD_REL * G_jj, or G_jj ~ 0)
+// marks a numerically dependent column: its row of R and column of R^{-1}
+// are 0. R^{-1} by back substitution from R in LDS, column c in lane c.
 template <int K>
-__device__ void w_chol_inv(const double* G, double* R, double* Rinv) {
-    const int c = lane_id();
-    for (int e = c; e < K * K; e += WAVE) R[e] = 0.0;
-    wave_sync();
+__device__ void w_chol_inv2(const double* G0, double* R0, double* Ri0, const double* G1, double* R1,
+                            double* Ri1) {
+    static_assert(K <= 32, "one column per lane of a half wave");
+    const int lane = lane_id();
+    const int h = lane >> 5, c = lane & 31;
+    const double* G = h ? G1 : G0;
+    double g[K], r[K], inv[K], x[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) g[i] = c < K ? G[i * K + c] : 0.0;
+#pragma unroll
     for (int j = 0; j < K; ++j) {
-        if (c == j) {
-            const double g = G[j * K + j];
-            double d = g;
-            for (int k = 0; k < j; ++k) d -= R[k * K + j] * R[k * K + j];
-            R[j * K + j] = (g > 1e-300 && d > CHOL_DEAD_REL * g) ? sqrt(d) : 0.0;
+        const double d = h ? readlane64(g[j], 32 + j) : readlane64(g[j], j);
+        const double gjj = G[j * K + j];
+        const bool live = gjj > 1e-300 && d > CHOL_DEAD_REL * gjj;
+        const double rjj = live ? sqrt(d) : 0.0;
+        const double ivj = live ? 1.0 / rjj : 0.0;
+        inv[j] = ivj;
+        r[j] = (c == j) ? rjj : (c > j ? g[j] * ivj : 0.0);   // R[j][c]
+#pragma unroll
+        for (int i = j + 1; i < K; ++i) {
+            const double rji = h ? readlane64(r[j], 32 + i) : readlane64(r[j], i);
+            g[i] = fma(-rji, r[j], g[i]);
         }
-        wave_sync();
-        if (c > j && c < K) {
-            const double rjj = R[j * K + j];
-            double v = 0.0;
-            if (rjj != 0.0) {
-                v = G[j * K + c];
-                for (int k = 0; k < j; ++k) v -= R[k * K + j] * R[k * K + c];
-                v /= rjj;
-            }
-            R[j * K + c] = v;
-        }
-        wave_sync();
+    }
+    double* R = h ? R1 : R0;
+    double* Ri = h ? Ri1 : Ri0;
+    if (c < K) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) R[i * K + c] = r[i];
+    }
+    wave_sync();
+    // back substitution with R read from LDS (same address in all lanes of a half)
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+        double v = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = i + 1; k < K; ++k) v = fma(-R[i * K + k], x[k], v);
+        x[i] = v * inv[i];
     }
     if (c < K) {
-        double x[K];
-        for (int i = K - 1; i >= 0; --i) {
-            const double rii = R[i * K + i];
-            double v = 0.0;
-            if (rii != 0.0) {
-                v = (i == c) ? 1.0 : 0.0;
-                for (int k = i + 1; k < K; ++k) v -= R[i * K + k] * x[k];
-                v /= rii;
-            }
-            x[i] = v;
-        }
-        for (int i = 0; i < K; ++i) Rinv[i * K + c] = x[i];
+#pragma unroll
+        for (int i = 0; i < K; ++i) Ri[i * K + c] = x[i];
     }
     wave_sync();
 }
@@ -306,11 +322,14 @@ __device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, do
                 al = group_sum<LP>(al);
                 be = group_sum<LP>(be);
                 ga = group_sum<LP>(ga);
-                if (fabs(ga) > JACOBI_EPS * sqrt(al * be) && fabs(ga) > floor_abs) {
-                    const double zt = (be - al) / (2.0 * ga);
-                    const double t = fabs(zt) > 1e100 ? 0.5 / zt
-                                                      : copysign(1.0, zt) / (fabs(zt) + sqrt(1.0 + zt * zt));
-                    const double c = 1.0 / sqrt(1.0 + t * t);
+                if (ga * ga > (JACOBI_EPS * JACOBI_EPS) * (al * be) && fabs(ga) > floor_abs) {
+                    // tangent of the rotation angle: the root of smaller modulus of
+                    // t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga), written
+                    // without forming zeta
+                    const double dl = be - al;
+                    const double hyp = sqrt(fma(dl, dl, 4.0 * ga * ga));
+                    const double t = (dl >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(dl) + hyp);
+                    const double c = rsqrt(fma(t, t, 1.0));
                     const double s = c * t;
 #pragma unroll
                     for (int u = 0; u < E; ++u) {
@@ -389,8 +408,7 @@ __device__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, con
     __shared__ double Ma[N * N], Mv[N * N], Um[N * N], Vm[N * N], sg[N];
     __shared__ double x1[K * K], x2[K * K], z1[K * K], z2[K * K], t1[K * K], t2[K * K];
     const int lane = lane_id();
-    w_chol_inv<K>(g1, r1, r1i);
-    w_chol_inv<K>(g2, r2, r2i);
+    w_chol_inv2<K>(g1, r1, r1i, g2, r2, r2i);
     for (int e = lane; e < N * N; e += WAVE) {
         const int col = e / N, rw = e % N;
         double v = 0.0;
@@ -504,8 +522,10 @@ __device__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, con
 
 // ---- kernel 1: gather partial products, C*, residual, stopping rule ----------
 //
-// 1024 threads, four adjacent lanes per row: the lanes of a quad sum disjoint
-// subsets of the streaming-pass tiles, then a fixed-order quad reduction.
+// 1024 threads, GATHER_SPLIT adjacent lanes per row: the lanes of a row sum
+// disjoint subsets of the streaming-pass tiles (one round of loads), then a
+// fixed-order DPP reduction; 128 rows per workgroup, one workgroup per CU.
+// The last workgroup sums the per-workgroup partials with all its threads.
 // FP32 (gram_form): also the Grams of Y1 and Y2, and the whole 2K x 2K step in
 // the tail. FP64: only C* and C2; the complement kernel forms W explicitly.
 template <typename T, int K>
@@ -528,28 +548,26 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
 #pragma unroll
     for (int t = 0; t < K; ++t) y[t] = 0.0;
     if (row < nrows) {
-        int c = chunk;
-        for (; c + 3 * GATHER_SPLIT < ntiles; c += 4 * GATHER_SPLIT) {
-            Acc v[4][K];
+        // up to LR partials per lane and round, all loads in flight at once
+        constexpr int LR0 = 48 / (K * (int)(sizeof(Acc) / 4));
+        constexpr int LR = LR0 < 2 ? 2 : (LR0 > 8 ? 8 : LR0);
+        for (int c0 = chunk; c0 < ntiles; c0 += LR * GATHER_SPLIT) {
+            Acc v[LR][K];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < LR; ++u) {
+                const int c = c0 + u * GATHER_SPLIT;
 #pragma unroll
-                for (int t = 0; t < K; ++t) v[u][t] = P[((size_t)(c + u * GATHER_SPLIT) * nrows + row) * K + t];
+                for (int t = 0; t < K; ++t) v[u][t] = c < ntiles ? P[((size_t)c * nrows + row) * K + t] : Acc(0);
+            }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < LR; ++u)
 #pragma unroll
                 for (int t = 0; t < K; ++t) y[t] += static_cast<double>(v[u][t]);
         }
-        for (; c < ntiles; c += GATHER_SPLIT)
-#pragma unroll
-            for (int t = 0; t < K; ++t) y[t] += static_cast<double>(P[((size_t)c * nrows + row) * K + t]);
     }
-    // quad reduction (lanes 4s..4s+3 hold the chunks of row s)
+    // reduction over the GATHER_SPLIT adjacent lanes of a row
 #pragma unroll
-    for (int t = 0; t < K; ++t) {
-        y[t] += dpp64<0xB1>(y[t]);
-        y[t] += dpp64<0x4E>(y[t]);
-    }
+    for (int t = 0; t < K; ++t) y[t] = group_sum<GATHER_SPLIT>(y[t]);
     const bool holder = chunk == 0 && row < nrows;
     double f[K];   // the row of U_f (U side) or V_f (V side)
 #pragma unroll
@@ -572,20 +590,17 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     if (!last_block_arrives(&ctrl->cnt[CNT_GATHER], &flag)) return;
 
     // ---- last workgroup: all threads sum the partials, then one wave ----
-    __shared__ double craw[K * K], craw2[K * K], ru[K * K], rv[K * K], cs[K * K], c2[K * K], tmp[K * K];
-    __shared__ double gy1[K * K], gy2[K * K], g1[K * K], g2[K * K];
+    __shared__ double sums[4 * K * K], ru[K * K], rv[K * K], cs[K * K], c2[K * K], tmp[K * K];
+    __shared__ double g1[K * K], g2[K * K];
     __shared__ double part[GATHER_THREADS], rsum[2];
+    double* craw = sums;              // U_f^T Y1
+    double* craw2 = sums + K * K;     // V_f^T Y2
+    double* gy1 = sums + 2 * K * K;   // Gram(Y1)
+    double* gy2 = sums + 3 * K * K;   // Gram(Y2)
     const int gV = gridDim.x - gU;
     const bool sigma_stage = ctrl->stage == STAGE_SIGMA_D;
     block_resid<GATHER_THREADS>(a.resid, a.n_tiles, sigma_stage, part, rsum);
-    if (GRAM) {
-        const SumJob jobs[4] = {{0, gU, 0, craw}, {gU, gV, 0, craw2}, {0, gU, KMAX * KMAX, gy1},
-                                {gU, gV, KMAX * KMAX, gy2}};
-        block_sum_partials<K * K, 4, GATHER_THREADS>(a.gpart, jobs, part);
-    } else {
-        const SumJob jobs[2] = {{0, gU, 0, craw}, {gU, gV, 0, craw2}};
-        block_sum_partials<K * K, 2, GATHER_THREADS>(a.gpart, jobs, part);
-    }
+    block_sum_partials<K * K, GRAM ? 4 : 2, GATHER_THREADS>(a.gpart, gU, gV, sums, part);
     if (threadIdx.x >= WAVE) return;
     const int lane = lane_id();
     w_load<K>(a.small->RUinv, ru);
@@ -682,11 +697,10 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_complement(PanelArgs a) {
     }
     rows_outer_sum<K, PANEL_THREADS>(w, w, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
     if (!last_block_arrives(&ctrl->cnt[CNT_COMPLEMENT], &flag)) return;
-    __shared__ double g1[K * K], g2[K * K], part[PANEL_THREADS];
-    {
-        const SumJob jobs[2] = {{0, a.gU, 0, g1}, {a.gU, a.gV, 0, g2}};
-        block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, jobs, part);
-    }
+    __shared__ double gg[2 * K * K], part[PANEL_THREADS];
+    double* g1 = gg;
+    double* g2 = gg + K * K;
+    block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, a.gU, a.gV, gg, part);
     if (threadIdx.x >= WAVE) return;
     if (lane_id() == 0) ctrl->cnt[CNT_COMPLEMENT] = 0;
     w_svd_tail<K>(a, ctrl, cs, c2, g1, g2, ru, rv, false);
@@ -774,17 +788,15 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
     }
     rows_outer_sum<K, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
     if (!last_block_arrives(&ctrl->cnt[CNT_UPDATE], &flag)) return;
-    __shared__ double g[K * K], gb[K * K], rr[K * K], ri[K * K], part[PANEL_THREADS];
-    {
-        const SumJob jobs[2] = {{0, a.gU, 0, g}, {a.gU, a.gV, 0, gb}};
-        block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, jobs, part);
-    }
+    __shared__ double gg[2 * K * K], rr[K * K], ri[K * K], rr2[K * K], ri2[K * K], part[PANEL_THREADS];
+    double* g = gg;
+    double* gb = gg + K * K;
+    block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, a.gU, a.gV, gg, part);
     if (threadIdx.x >= WAVE) return;
     const bool exact = a.mode == UPDATE_ENTER_EXACT;
-    w_chol_inv<K>(g, rr, ri);
+    w_chol_inv2<K>(g, rr, ri, gb, rr2, ri2);
     w_store<K>(ri, exact ? a.small->RAinv : a.small->RUinv);
-    w_chol_inv<K>(gb, rr, ri);
-    w_store<K>(ri, exact ? a.small->RBinv : a.small->RVinv);
+    w_store<K>(ri2, exact ? a.small->RBinv : a.small->RVinv);
     const int lane = lane_id();
     if (a.sigma_dst && lane < K) a.sigma_dst[lane] = sig[lane];
     if (lane == 0) {
@@ -850,16 +862,14 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_start(PanelArgs a) {
     }
     rows_outer_sum<K, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
     if (!last_block_arrives(&ctrl->cnt[CNT_START], &flag)) return;
-    __shared__ double g[K * K], gb[K * K], rr[K * K], ri[K * K], part[PANEL_THREADS];
-    {
-        const SumJob jobs[2] = {{0, a.gU, 0, g}, {a.gU, a.gV, 0, gb}};
-        block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, jobs, part);
-    }
+    __shared__ double gg[2 * K * K], rr[K * K], ri[K * K], rr2[K * K], ri2[K * K], part[PANEL_THREADS];
+    double* g = gg;
+    double* gb = gg + K * K;
+    block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, a.gU, a.gV, gg, part);
     if (threadIdx.x >= WAVE) return;
-    w_chol_inv<K>(g, rr, ri);
+    w_chol_inv2<K>(g, rr, ri, gb, rr2, ri2);
     w_store<K>(ri, a.small->RUinv);
-    w_chol_inv<K>(gb, rr, ri);
-    w_store<K>(ri, a.small->RVinv);
+    w_store<K>(ri2, a.small->RVinv);
     if (lane_id() == 0) ctrl->cnt[CNT_START] = 0;
 }
 
