@@ -54,6 +54,16 @@ extern "C" {
 
 /* ---- flags ------------------------------------------------------------- */
 #define RPCA_FLAG_NO_TRIM 1u  /* AccAltProj without trim (Section 3): U~ = U_k, V~ = V_k */
+/* Mixed-precision form (RPCA_F32 only): the two tangent products
+ * Y1 = (D - S_k) V~ and Y2 = (D - S_k)^T U~ of a loop body run on the matrix
+ * cores with BF16 operands and FP32 accumulation; the rebuild of L_k, the
+ * threshold, the residual and err_k stay FP32, as does all small algebra
+ * (FP64). In rpca_solve, body k (which computes err_k and L_{k+1}) takes BF16
+ * products while err_j >= mixed_err for every j <= k - 2 (bodies 0 and 1
+ * always do: the host decides one body ahead); every later body is the FP32
+ * one. rpca_step takes BF16 products while the state's err >= mixed_err (or
+ * is unknown). Not part of the paper: a precision choice of this library. */
+#define RPCA_FLAG_MIXED 2u
 
 /* Largest supported rank r and init block p. */
 #define RPCA_MAX_RANK 16
@@ -75,6 +85,8 @@ typedef struct rpca_params {
     int32_t  init_max_passes; /* cap on passes over D per init stage; 0 = default (40)      */
     uint32_t flags;        /* RPCA_FLAG_*                                                    */
     uint64_t seed;         /* seeds the start block of the initial truncated SVD             */
+    double   mixed_err;    /* with RPCA_FLAG_MIXED: BF16-product bodies while err_k >= this;
+                              <= 0 selects the default 1e-3                                  */
 } rpca_params;
 
 /* Iterate (L_k, S_k): L_k = U diag(sigma) V^T, S_k = T_zeta(D - L_k). The three
@@ -143,7 +155,8 @@ int rpca_materialize(const void *D, const rpca_params *p, const rpca_state *st,
  *   Y1 = Z V_t   (device m x r, FP64)    Y2 = Z^T U_t (device n x r, FP64)
  *   *resid2 = sum over |x_ij| <= zeta of x_ij^2   (host scalar),
  * where U_t (m x r) and V_t (n x r) are device FP64 bases. Inputs are rounded
- * to dtype before the pass, as inside rpca_step. */
+ * to dtype before the pass, as inside rpca_step; with RPCA_FLAG_MIXED the
+ * products are the BF16 matrix-core ones. */
 int rpca_tangent_products(const void *D, const rpca_params *p,
                           const double *A_L, const double *B_L, double zeta,
                           const double *U_t, const double *V_t,
@@ -154,10 +167,13 @@ int rpca_tangent_products(const void *D, const rpca_params *p,
  * streaming pass over D (the only kernel reading the m x n data) is bracketed
  * by two HIP events recorded on the caller's stream; a pass queued after a
  * loop has stopped, which does no work, is not counted. rpca_profile_read
- * waits for the recorded passes and returns their summed duration in ms and
- * their number since the previous read, then resets both. Disabling keeps
+ * waits for the recorded passes and returns, per kind of pass, their summed
+ * duration in ms and their number since the previous read, then resets them:
+ * stream_ms and stream_launches are arrays of RPCA_PROF_KINDS entries, [0] the
+ * passes in the dtype of D, [1] the passes with BF16 products. Disabling keeps
  * the totals for a final read. Intended for benchmarks: the events add a few
  * microseconds of queue work per pass. */
+#define RPCA_PROF_KINDS 2
 int rpca_profile_enable(int on);
 int rpca_profile_read(double *stream_ms, int64_t *stream_launches);
 

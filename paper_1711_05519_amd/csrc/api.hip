@@ -24,6 +24,7 @@ namespace {
 thread_local int g_last_hip_error = 0;
 
 constexpr int DEFAULT_INIT_MAX_PASSES = 40;
+constexpr double DEFAULT_MIXED_ERR = 1e-3;
 constexpr int MAX_DEVICES = 64;
 
 #define HIP_TRY(expr)                                    \
@@ -85,9 +86,13 @@ struct Profiler {
     std::mutex mu;
     bool on = false;
     std::vector<hipEvent_t> pool;                        // free events
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-    double ms = 0.0;
-    int64_t launches = 0;
+    struct Rec {
+        hipEvent_t e0, e1;
+        int kind;
+    };
+    std::vector<Rec> pending;
+    double ms[RPCA_PROF_KINDS] = {0.0, 0.0};
+    int64_t launches[RPCA_PROF_KINDS] = {0, 0};
 };
 Profiler g_prof;
 
@@ -104,20 +109,21 @@ hipEvent_t prof_event() {
 
 int prof_collect_locked() {
     for (auto& pr : g_prof.pending) {
-        HIP_TRY(hipEventSynchronize(pr.second));
+        HIP_TRY(hipEventSynchronize(pr.e1));
         float t = 0.f;
-        HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second));
-        g_prof.ms += t;
-        g_prof.launches += 1;
-        g_prof.pool.push_back(pr.first);
-        g_prof.pool.push_back(pr.second);
+        HIP_TRY(hipEventElapsedTime(&t, pr.e0, pr.e1));
+        g_prof.ms[pr.kind] += t;
+        g_prof.launches[pr.kind] += 1;
+        g_prof.pool.push_back(pr.e0);
+        g_prof.pool.push_back(pr.e1);
     }
     g_prof.pending.clear();
     return RPCA_OK;
 }
 
-// Launch of the streaming pass, bracketed by events when profiling is on.
-int stream_launch(const StreamArgs& a, int K, int dtype, bool rebuild, hipStream_t s) {
+// Launch of the streaming pass (mx: products on the matrix cores in BF16),
+// bracketed by events when profiling is on.
+int stream_launch(const StreamArgs& a, int K, int dtype, bool rebuild, bool mx, hipStream_t s) {
     std::lock_guard<std::mutex> lock(g_prof.mu);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (g_prof.on) {
@@ -127,10 +133,11 @@ int stream_launch(const StreamArgs& a, int K, int dtype, bool rebuild, hipStream
         if (!e0 || !e1) return RPCA_EHIP;
         HIP_TRY(hipEventRecord(e0, s));
     }
-    HIP_TRY(launch_stream(a, K, dtype, rebuild, s));
+    if (mx) HIP_TRY(launch_stream_mx(a, K, rebuild, s));
+    else HIP_TRY(launch_stream(a, K, dtype, rebuild, s));
     if (g_prof.on) {
         HIP_TRY(hipEventRecord(e1, s));
-        g_prof.pending.emplace_back(e0, e1);
+        g_prof.pending.push_back({e0, e1, mx ? 1 : 0});
     }
     return RPCA_OK;
 }
@@ -141,9 +148,9 @@ void prof_drop_last() {
     if (g_prof.on && !g_prof.pending.empty()) {
         auto pr = g_prof.pending.back();
         g_prof.pending.pop_back();
-        (void)hipEventSynchronize(pr.second);
-        g_prof.pool.push_back(pr.first);
-        g_prof.pool.push_back(pr.second);
+        (void)hipEventSynchronize(pr.e1);
+        g_prof.pool.push_back(pr.e0);
+        g_prof.pool.push_back(pr.e1);
     }
 }
 
@@ -167,7 +174,9 @@ int validate(const rpca_params* p) {
     if (!is_fin(p->tol) || !(p->tol > 0)) return RPCA_EINVAL;
     if (!(p->flags & RPCA_FLAG_NO_TRIM) && (!is_fin(p->mu) || !(p->mu > 0))) return RPCA_EINVAL;
     if (p->max_iter < 0 || p->init_max_passes < 0) return RPCA_EINVAL;
-    if (p->flags & ~RPCA_FLAG_NO_TRIM) return RPCA_EINVAL;
+    if (p->flags & ~(RPCA_FLAG_NO_TRIM | RPCA_FLAG_MIXED)) return RPCA_EINVAL;
+    if ((p->flags & RPCA_FLAG_MIXED) && p->dtype != RPCA_F32) return RPCA_EINVAL;
+    if (!(p->mixed_err == p->mixed_err) || isinf(p->mixed_err)) return RPCA_EINVAL;
     if (p->init_block != 0) {
         if (p->init_block < p->r || p->init_block > KMAX ||
             2 * (int64_t)p->init_block > (p->m < p->n ? p->m : p->n))
@@ -245,6 +254,8 @@ struct Ctx {
     hipStream_t s;
     DeviceInfo* dev;
     int dtype;
+    bool mixed;          // RPCA_FLAG_MIXED: BF16-product bodies while err_k >= mixed_err
+    double mixed_err;
     Ctrl* ctrl() const { return reinterpret_cast<Ctrl*>(ws + L.off_ctrl); }
     Small* small() const { return reinterpret_cast<Small*>(ws + L.off_small); }
     double* err_hist() const { return reinterpret_cast<double*>(ws + L.off_hist); }
@@ -263,6 +274,8 @@ int make_ctx(const rpca_params* p, void* ws, size_t ws_bytes, void* stream, Ctx*
     c->s = static_cast<hipStream_t>(stream);
     c->dev = dev;
     c->dtype = p->dtype;
+    c->mixed = (p->flags & RPCA_FLAG_MIXED) != 0;
+    c->mixed_err = p->mixed_err > 0 ? p->mixed_err : DEFAULT_MIXED_ERR;
     return RPCA_OK;
 }
 
@@ -300,9 +313,10 @@ Ctrl base_ctrl(const Ctx& c, int stage, double zeta, int k, double normD2, int w
 struct Geo {
     int TM, n_rt;
 };
-Geo geo_for(const Ctx& c, int K, bool rebuild) {
+Geo geo_for(const Ctx& c, int K, bool rebuild, bool mx = false) {
     const int m = (int)c.p->m;
-    const int slots = stream_occupancy(K, c.dtype, rebuild) * c.dev->cus;
+    const int occ = mx ? stream_mx_occupancy(K, rebuild) : stream_occupancy(K, c.dtype, rebuild);
+    const int slots = occ * c.dev->cus;
     int n_rt = n_rt_for(m, c.L.n_ct, slots < STREAM_MAX_SLOTS ? slots : STREAM_MAX_SLOTS);
     int TM = (m + n_rt - 1) / n_rt;
     TM = (TM + STREAM_WAVES - 1) / STREAM_WAVES * STREAM_WAVES;
@@ -375,12 +389,12 @@ int setup(const Ctx& c, const Ctrl& t) {
 // One loop body. FP32: stream pass, gather (with the 2r x 2r step), update.
 // FP64: stream pass, gather, complement (explicit W), update.
 int enqueue_body(const Ctx& c, const void* D, int K, int body, double* state_U, double* state_V,
-                 double* state_sigma, bool with_hist) {
+                 double* state_sigma, bool with_hist, bool mx = false) {
     const bool rebuild = body != BODY_INIT;
     const bool fp32 = c.dtype == RPCA_F32;
-    const Geo g = geo_for(c, K, rebuild);
+    const Geo g = geo_for(c, K, rebuild, mx);
     StreamArgs sa = stream_args(c, D, body, g);
-    RPCA_TRY(stream_launch(sa, K, c.dtype, rebuild, c.s));
+    RPCA_TRY(stream_launch(sa, K, c.dtype, rebuild, mx, c.s));
     PanelArgs pa = panel_args(c, g);
     pa.body = body;
     if (with_hist) {
@@ -425,7 +439,8 @@ int enqueue_enter(const Ctx& c, const double* srcU, const double* srcV, int64_t 
     return RPCA_OK;
 }
 
-// Runs queued bodies until `finished(status)`; keeps one body queued ahead.
+// Runs queued bodies until `finished(status, b)`, called once body b has
+// completed (b = 0, 1, ...); keeps one body queued ahead.
 template <typename Enq, typename Fin>
 int pipelined_loop(const Ctx& c, int max_bodies, Enq enqueue, Fin finished) {
     constexpr int NEV = 4;
@@ -443,7 +458,7 @@ int pipelined_loop(const Ctx& c, int max_bodies, Enq enqueue, Fin finished) {
             if (e != hipSuccess) { g_last_hip_error = (int)e; rc = RPCA_EHIP; break; }
             HostStatus st;
             memcpy(&st, (const void*)c.dev->status_host, sizeof(st));
-            if (finished(st)) {
+            if (finished(st, b - 1)) {
                 prof_drop_last();   // body b was queued after the stop: a no-op
                 break;
             }
@@ -474,7 +489,7 @@ int run_init(const Ctx& c, const void* D, rpca_state* st, Ctrl* ctrl_out) {
     int rc = pipelined_loop(
         c, max_bodies,
         [&]() { return enqueue_body(c, D, P, BODY_INIT, nullptr, nullptr, nullptr, false); },
-        [&](const HostStatus& hs) { return hs.stage >= STAGE_INIT_DONE; });
+        [&](const HostStatus& hs, int) { return hs.stage >= STAGE_INIT_DONE; });
     RPCA_TRY(rc);
     Ctrl now;
     RPCA_TRY(read_ctrl(c, &now));
@@ -491,7 +506,7 @@ int run_init(const Ctx& c, const void* D, rpca_state* st, Ctrl* ctrl_out) {
 int threshold_pass(const Ctx& c, const void* D, bool rebuild) {
     const int K = c.p->r;
     const Geo g = geo_for(c, K, rebuild);
-    RPCA_TRY(stream_launch(stream_args(c, D, BODY_ANY, g), K, c.dtype, rebuild, c.s));
+    RPCA_TRY(stream_launch(stream_args(c, D, BODY_ANY, g), K, c.dtype, rebuild, false, c.s));
     HIP_TRY(launch_gather(panel_args(c, g), K, c.dtype, c.s));
     return RPCA_OK;
 }
@@ -528,10 +543,12 @@ int rpca_profile_read(double* stream_ms, int64_t* stream_launches) {
     if (!stream_ms || !stream_launches) return RPCA_EINVAL;
     std::lock_guard<std::mutex> lock(g_prof.mu);
     RPCA_TRY(prof_collect_locked());
-    *stream_ms = g_prof.ms;
-    *stream_launches = g_prof.launches;
-    g_prof.ms = 0.0;
-    g_prof.launches = 0;
+    for (int k = 0; k < RPCA_PROF_KINDS; ++k) {
+        stream_ms[k] = g_prof.ms[k];
+        stream_launches[k] = g_prof.launches[k];
+        g_prof.ms[k] = 0.0;
+        g_prof.launches[k] = 0;
+    }
     return RPCA_OK;
 }
 
@@ -588,10 +605,19 @@ int rpca_solve(const void* D, const rpca_params* p, rpca_state* st, double* err_
     t.active = 1;
     t.done = 0;
     RPCA_TRY(setup(c, t));
+    // Mixed form: body k + 1 is enqueued once body k - 1 has completed, so
+    // it takes BF16 products while err_{k-1} >= mixed_err (bodies 0 and 1
+    // always do); the first body with err below the level switches every
+    // later body to the FP32 pass. The decision reads err of a fixed body
+    // (the status ring), so it does not depend on timing.
+    bool use_mx = c.mixed;
     int rc = pipelined_loop(
         c, p->max_iter + 3,
-        [&]() { return enqueue_body(c, D, p->r, BODY_MAIN, st->U, st->V, st->sigma, true); },
-        [&](const HostStatus& hs) { return hs.done != 0; });
+        [&]() { return enqueue_body(c, D, p->r, BODY_MAIN, st->U, st->V, st->sigma, true, use_mx); },
+        [&](const HostStatus& hs, int b) {
+            if (use_mx && hs.err_ring[b & 7] < c.mixed_err) use_mx = false;
+            return hs.done != 0;
+        });
     RPCA_TRY(rc);
     Ctrl fin;
     RPCA_TRY(read_ctrl(c, &fin));
@@ -652,7 +678,8 @@ int rpca_step(const void* D, const rpca_params* p, rpca_state* st, void* ws, siz
     // Trim(L_k) and its orthonormal bases
     RPCA_TRY(enqueue_enter(c, st->U, st->V, K, st->sigma, nullptr, nullptr, nullptr));
     // products with Z_k, the 2r x 2r update, zeta_{k+1}; L_{k+1} overwrites the state
-    RPCA_TRY(enqueue_body(c, D, K, BODY_ANY, st->U, st->V, st->sigma, false));
+    const bool mx = c.mixed && !(st->err > 0 && st->err < c.mixed_err);
+    RPCA_TRY(enqueue_body(c, D, K, BODY_ANY, st->U, st->V, st->sigma, false, mx));
     // err_{k+1}: threshold pass at (L_{k+1}, zeta_{k+1})
     RPCA_TRY(threshold_pass(c, D, true));
     Ctrl t;
@@ -701,8 +728,8 @@ int rpca_tangent_products(const void* D, const rpca_params* p, const double* A_L
     HIP_TRY(launch_convert(B_L, c.ws + c.L.off_BL, p->n * K, nullptr, K, c.dtype, c.s));
     HIP_TRY(launch_convert(U_t, c.ws + c.L.off_Uf, p->m * K, nullptr, K, c.dtype, c.s));
     HIP_TRY(launch_convert(V_t, c.ws + c.L.off_Vf, p->n * K, nullptr, K, c.dtype, c.s));
-    const Geo g = geo_for(c, K, true);
-    RPCA_TRY(stream_launch(stream_args(c, D, BODY_ANY, g), K, c.dtype, true, c.s));
+    const Geo g = geo_for(c, K, true, c.mixed);
+    RPCA_TRY(stream_launch(stream_args(c, D, BODY_ANY, g), K, c.dtype, true, c.mixed, c.s));
     PanelArgs pa = panel_args(c, g);
     pa.Y1 = Y1;
     pa.Y2 = Y2;

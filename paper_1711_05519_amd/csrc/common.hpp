@@ -47,6 +47,7 @@ struct HostStatus {
     int32_t k;
     double err;
     double zeta;
+    double err_ring[8];  // err_k of loop body k in slot k & 7
 };
 
 // Control block at the start of the workspace (device memory).
@@ -79,6 +80,7 @@ struct Ctrl {
     double resid2;       // last residual sum (sum over |x| <= zeta of x^2)
     double sigma_dead;   // relative size below which a singular triplet of M is dropped
     double max_abs_D;    // max |D_ij| (from the init passes, where L = 0)
+    double err_ring[8];  // err_k of loop body k in slot k & 7 (published to the host)
     int32_t single;      // 1: D and the streamed factors are FP32
     int32_t pad_;
 };

@@ -84,6 +84,8 @@ enum GatherMode : int { GATHER_ONLY = 0, GATHER_WITH_SVD = 1 };
 // dtype: 0 = double, 1 = float
 // Workgroups of the streaming pass resident per CU (from the HIP occupancy API).
 int stream_occupancy(int K, int dtype, bool rebuild);
+int stream_mx_occupancy(int K, bool rebuild);
+hipError_t launch_stream_mx(const StreamArgs& a, int K, bool rebuild, hipStream_t s);
 hipError_t launch_stream(const StreamArgs& a, int K, int dtype, bool rebuild, hipStream_t s);
 hipError_t launch_materialize(const MaterializeArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_gather(const PanelArgs& a, int K, int dtype, hipStream_t s);

@@ -386,6 +386,7 @@ __device__ inline void publish_status(const PanelArgs& a, const Ctrl* c) {
         st.k = c->k;
         st.err = c->err;
         st.zeta = c->zeta;
+        for (int i = 0; i < 8; ++i) st.err_ring[i] = c->err_ring[i];
         *a.host_status = st;
         __threadfence_system();
     }
@@ -624,6 +625,7 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
             const double err = sqrt(rs / ctrl->normD2);
             ctrl->err = err;
             const int k = ctrl->k;
+            ctrl->err_ring[k & 7] = err;
             if (a.err_hist && k < a.hist_cap) { a.err_hist[k] = err; a.zeta_hist[k] = ctrl->zeta; }
             if (ctrl->want_stop && (err < ctrl->tol || k >= ctrl->max_iter)) {
                 ctrl->done = 1;

@@ -1,0 +1,336 @@
+// The streaming pass with the two tangent products on the matrix cores (the
+// mixed-precision form). Per element of D, in FP32 on the vector ALUs: the
+// rank-K rebuild of L, the threshold T_zeta, the residual (Section 2.1 and
+// Algorithm 1), exactly as in the FP32 pass. The thresholded tile Z = D - S is
+// then rounded to BF16 into LDS and both products
+//   Y1 = Z V_f  (m x K),   Y2 = Z^T U_f  (n x K)
+// run as v_mfma_f32_16x16x32_bf16 with FP32 accumulation; U_f and V_f are
+// rounded to BF16 as well. Only the products lose precision (BF16 operands,
+// relative error ~2^-9 per term); the threshold decisions, the residual and
+// err_k are the FP32 ones. The library switches to the FP32 pass once err_k
+// falls below a set level, so the final iterate is the FP32 method's.
+//
+// Layout: workgroup of 4 waves, tile TM rows x 256 columns; each wave takes
+// blocks of 32 rows (rows i0 + 32w, i0 + 32(w + 4), ...). Phase A: the lane
+// owns columns 4l..4l+3 of the tile, 4 rows per batch of loads, and writes the
+// BF16 values of Z row-major into its wave's LDS block (row pitch 260 BF16:
+// the pad spreads the column reads over the banks). Phase B: Y1 of the two
+// 16-row halves from row reads (8 consecutive columns per lane, the MFMA A
+// layout), Y2 of the sixteen 16-column blocks from column reads (8 consecutive
+// rows per lane). MFMA 16x16x32 lane layout: A row l%16, k = 8(l/16)+q;
+// B column l%16, k = 8(l/16)+q; C column l%16, rows 4(l/16)+r.
+// Partials are written in the FP32 pass's layout, so the gather is shared.
+
+#include "launch.hpp"
+
+namespace rpca {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MX_RB = 32;                 // rows per wave block
+constexpr int MX_PITCH = STREAM_TN + 4;   // BF16 per LDS row
+constexpr int MX_BATCH = 4;               // rows per batch of loads in phase A
+
+__device__ inline void mx_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline uint32_t pack2(float a, float b) {
+    const __bf16 ha = static_cast<__bf16>(a), hb = static_cast<__bf16>(b);
+    return (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+}
+
+__device__ inline __bf16 to_bf16(float x) { return static_cast<__bf16>(x); }
+
+// MX_BATCH rows x 4 columns of D for one lane (zeros outside the matrix).
+// FULL: the tile's 256 columns are inside D and rows are 16-byte aligned, so
+// only the (wave-uniform) row bound is checked.
+template <bool FULL>
+__device__ inline void mx_load_batch(const float* __restrict__ D, int64_t ldd, int i0, int i_hi, int jb, int nvalid,
+                                     float (&d)[MX_BATCH][4]) {
+#pragma unroll
+    for (int b = 0; b < MX_BATCH; ++b) {
+        const int i = i0 + b;
+        const float* p = D + (size_t)i * ldd + jb;
+        if constexpr (FULL) {
+            if (i < i_hi) {
+                const float4 v = *reinterpret_cast<const float4*>(p);
+                d[b][0] = v.x; d[b][1] = v.y; d[b][2] = v.z; d[b][3] = v.w;
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) d[b][s] = 0.f;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) d[b][s] = (i < i_hi && s < nvalid) ? p[s] : 0.f;
+        }
+    }
+}
+
+// Threshold and residual of one batch; Z in BF16 into the wave's LDS block.
+template <int K, bool REBUILD>
+__device__ inline void mx_compute_batch(const float (&d)[MX_BATCH][4], const float* __restrict__ AL, int i0, int i_hi,
+                                        int r_local, float zeta, const float (&bl)[4][K], uint16_t* zl, int lane,
+                                        float& rs, float& amax) {
+#pragma unroll
+    for (int b = 0; b < MX_BATCH; ++b) {
+        const int i = i0 + b;
+        float al[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) al[t] = (REBUILD && i < i_hi) ? AL[(size_t)i * K + t] : 0.f;
+        float z[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float dv = d[b][s];
+            float x = dv;
+            if constexpr (REBUILD) {
+#pragma unroll
+                for (int t = 0; t < K; ++t) x = fmaf(-al[t], bl[s][t], x);
+            } else {
+                amax = fmaxf(amax, fabsf(x));
+            }
+            const bool big = fabsf(x) > zeta;   // S_ij = x
+            const float e = big ? 0.f : x;
+            rs = fmaf(e, e, rs);
+            z[s] = big ? dv - x : dv;
+        }
+        uint2 w;
+        w.x = pack2(z[0], z[1]);
+        w.y = pack2(z[2], z[3]);
+        *reinterpret_cast<uint2*>(zl + (r_local + b) * MX_PITCH + 4 * lane) = w;
+    }
+}
+
+template <int K, bool REBUILD, bool FULL>
+__device__ inline void mx_tile(const float* __restrict__ D, const float* __restrict__ AL,
+                               const float* __restrict__ Uf, float* __restrict__ P1, const StreamGeom& g, float zeta,
+                               int ct, int i_lo, int i_hi, int wave, int lane, int jb, int nvalid,
+                               const float (&bl)[4][K], const bf16x8* vl, uint16_t* zl, f32x4 (&acc2)[STREAM_TN / 16],
+                               double& res, float& amax) {
+    const int lr = lane & 15, lg = lane >> 4;
+    float ba[MX_BATCH][4], bb[MX_BATCH][4];
+    int i0 = i_lo + MX_RB * wave;
+    if (i0 < i_hi) mx_load_batch<FULL>(D, g.ldd, i0, i_hi, jb, nvalid, ba);
+    for (; i0 < i_hi; i0 += MX_RB * STREAM_WAVES) {
+        float rs = 0.f;
+        // phase A: batches of MX_BATCH rows in two register buffers; the loads
+        // of the next batch (or of the next block's first batch) are in flight
+        // while one is computed
+        const int i_next = i0 + MX_RB * STREAM_WAVES;
+#pragma unroll 1
+        for (int bt = 0; bt < MX_RB / MX_BATCH; bt += 2) {
+            mx_load_batch<FULL>(D, g.ldd, i0 + MX_BATCH * (bt + 1), i_hi, jb, nvalid, bb);
+            mx_compute_batch<K, REBUILD>(ba, AL, i0 + MX_BATCH * bt, i_hi, MX_BATCH * bt, zeta, bl, zl, lane, rs,
+                                         amax);
+            // rows at or past i_hi load as zeros: a partial block computes zeros
+            const int inx = (bt + 2 < MX_RB / MX_BATCH) ? i0 + MX_BATCH * (bt + 2) : i_next;
+            mx_load_batch<FULL>(D, g.ldd, inx, i_hi, jb, nvalid, ba);
+            mx_compute_batch<K, REBUILD>(bb, AL, i0 + MX_BATCH * (bt + 1), i_hi, MX_BATCH * (bt + 1), zeta, bl, zl,
+                                         lane, rs, amax);
+        }
+        res += static_cast<double>(rs);
+        mx_wave_sync();
+
+        // phase B, Y1: rows i0 + 16h + lr, columns 32kb + 8lg + q
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            f32x4 a1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < STREAM_TN / 32; ++kb) {
+                const uint16_t* src = zl + (16 * h + lr) * MX_PITCH + 32 * kb + 8 * lg;
+                const uint2 w0 = *reinterpret_cast<const uint2*>(src);
+                const uint2 w1 = *reinterpret_cast<const uint2*>(src + 4);
+                bf16x8 A;
+                A[0] = __builtin_bit_cast(__bf16, (uint16_t)(w0.x & 0xffff));
+                A[1] = __builtin_bit_cast(__bf16, (uint16_t)(w0.x >> 16));
+                A[2] = __builtin_bit_cast(__bf16, (uint16_t)(w0.y & 0xffff));
+                A[3] = __builtin_bit_cast(__bf16, (uint16_t)(w0.y >> 16));
+                A[4] = __builtin_bit_cast(__bf16, (uint16_t)(w1.x & 0xffff));
+                A[5] = __builtin_bit_cast(__bf16, (uint16_t)(w1.x >> 16));
+                A[6] = __builtin_bit_cast(__bf16, (uint16_t)(w1.y & 0xffff));
+                A[7] = __builtin_bit_cast(__bf16, (uint16_t)(w1.y >> 16));
+                a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, vl[kb * WAVE + lane], a1, 0, 0, 0);
+                if ((kb & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+            if (lr < K) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + 16 * h + 4 * lg + r;
+                    if (i < i_hi) P1[((size_t)ct * g.m + i) * K + lr] = a1[r];
+                }
+            }
+        }
+        // phase B, Y2: B operand U_f rows i0 + 8lg + q, column lr
+        bf16x8 uB;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = i0 + 8 * lg + q;
+            uB[q] = to_bf16((lr < K && i < i_hi) ? Uf[(size_t)i * K + lr] : 0.f);
+        }
+        // groups of 4 column blocks: the scheduling barrier keeps the reads of
+        // a group next to its MFMAs (hoisting all 128 reads costs occupancy)
+#pragma unroll
+        for (int cb = 0; cb < STREAM_TN / 16; ++cb) {
+            bf16x8 A;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                A[q] = __builtin_bit_cast(__bf16, zl[(8 * lg + q) * MX_PITCH + 16 * cb + lr]);
+            acc2[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, uB, acc2[cb], 0, 0, 0);
+            if ((cb & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        mx_wave_sync();
+    }
+}
+
+template <int K, bool REBUILD>
+__global__ __launch_bounds__(STREAM_THREADS) void k_stream_mx(
+    const float* __restrict__ D, const float* __restrict__ AL, const float* __restrict__ BL,
+    const float* __restrict__ Uf, const float* __restrict__ Vf, float* __restrict__ P1, float* __restrict__ P2,
+    double* __restrict__ resid, const Ctrl* __restrict__ ctrl, StreamGeom g) {
+    static_assert(K <= 16, "MFMA N = 16 holds up to 16 columns");
+    if (!body_runs(ctrl, g.body)) return;
+    const float zeta = static_cast<float>(ctrl->zeta);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int ct = blockIdx.x % g.n_ct;
+    const int rt = blockIdx.x / g.n_ct;
+    const int c0 = ct * STREAM_TN;
+    const int jb = c0 + lane * 4;
+    const int nvalid = min(max(g.n - jb, 0), 4);
+    const int i_lo = rt * g.TM;
+    const int i_hi = min(g.m, i_lo + g.TM);
+    const int lr = lane & 15, lg = lane >> 4;   // MFMA row/column index and k group
+
+    __shared__ uint16_t zbuf[STREAM_WAVES][MX_RB * MX_PITCH];
+    __shared__ double red[STREAM_WAVES];
+    uint16_t* zl = zbuf[wave];
+    // B operands of Y1 in LDS, one 16-byte vector per (32-column block, lane):
+    // V_f rows c0 + 32kb + 8lg + q, column lr (zero when lr >= K)
+    __shared__ bf16x8 vl[(STREAM_TN / 32) * WAVE];
+    for (int e = threadIdx.x; e < (STREAM_TN / 32) * WAVE; e += STREAM_THREADS) {
+        const int kb = e / WAVE, ln = e % WAVE;
+        const int t = ln & 15, grp = ln >> 4;
+        bf16x8 v;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = c0 + 32 * kb + 8 * grp + q;
+            v[q] = to_bf16((t < K && j < g.n) ? Vf[(size_t)j * K + t] : 0.f);
+        }
+        vl[e] = v;
+    }
+    __syncthreads();
+
+    float bl[4][K];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int t = 0; t < K; ++t) bl[s][t] = (REBUILD && s < nvalid) ? BL[(size_t)(jb + s) * K + t] : 0.f;
+    f32x4 acc2[STREAM_TN / 16];
+#pragma unroll
+    for (int cb = 0; cb < STREAM_TN / 16; ++cb) acc2[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    double res = 0.0;
+    float amax = 0.f;
+    const bool full = g.vec_ok && c0 + STREAM_TN <= g.n;   // uniform per workgroup
+    if (full)
+        mx_tile<K, REBUILD, true>(D, AL, Uf, P1, g, zeta, ct, i_lo, i_hi, wave, lane, jb, nvalid, bl, vl, zl, acc2,
+                                  res, amax);
+    else
+        mx_tile<K, REBUILD, false>(D, AL, Uf, P1, g, zeta, ct, i_lo, i_hi, wave, lane, jb, nvalid, bl, vl, zl, acc2,
+                                   res, amax);
+
+    // Y2 partial of the tile: sum of the four waves through LDS (fixed order),
+    // lane holds columns 16cb + 4lg + r, column lr of Y2
+    __syncthreads();
+    float* sm = reinterpret_cast<float*>(&zbuf[0][0]);   // STREAM_TN * K floats
+    for (int w = 0; w < STREAM_WAVES; ++w) {
+        if (wave == w && lr < K) {
+#pragma unroll
+            for (int cb = 0; cb < STREAM_TN / 16; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int idx = (16 * cb + 4 * lg + r) * K + lr;
+                    sm[idx] = (w == 0) ? acc2[cb][r] : sm[idx] + acc2[cb][r];
+                }
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < STREAM_TN * K; idx += STREAM_THREADS) {
+        const int col = c0 + idx / K;
+        if (col < g.n) P2[((size_t)rt * g.n + col) * K + (idx % K)] = sm[idx];
+    }
+    const double rtot = block_sum_256(res, red);
+    if (threadIdx.x == 0) resid[blockIdx.x] = rtot;
+    if constexpr (!REBUILD) {
+        double v = static_cast<double>(amax);
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, WAVE));
+        if (lane == 0) red[wave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double mx = red[0];
+            for (int w = 1; w < STREAM_WAVES; ++w) mx = fmax(mx, red[w]);
+            resid[gridDim.x + blockIdx.x] = mx;
+        }
+    }
+}
+
+template <bool REBUILD>
+hipError_t mx_dispatch(const StreamArgs& a, int K, hipStream_t s) {
+    const dim3 grid((unsigned)(a.n_ct * a.n_rt)), block(STREAM_THREADS);
+    StreamGeom geom;
+    geom.ldd = a.ldd;
+    geom.m = a.m;
+    geom.n = a.n;
+    geom.TM = a.TM;
+    geom.n_ct = a.n_ct;
+    geom.n_rt = a.n_rt;
+    geom.vec_ok = a.vec_ok;
+    geom.body = a.body;
+    switch (K) {
+#define RPCA_CASE(KK)                                                                                        \
+    case KK:                                                                                                 \
+        hipLaunchKernelGGL((k_stream_mx<KK, REBUILD>), grid, block, 0, s, static_cast<const float*>(a.D),    \
+                           static_cast<const float*>(a.AL), static_cast<const float*>(a.BL),                 \
+                           static_cast<const float*>(a.Uf), static_cast<const float*>(a.Vf),                 \
+                           static_cast<float*>(a.P1), static_cast<float*>(a.P2), a.resid, a.ctrl, geom);     \
+        break;
+        RPCA_CASE(1) RPCA_CASE(2) RPCA_CASE(3) RPCA_CASE(4) RPCA_CASE(5) RPCA_CASE(6)
+        RPCA_CASE(7) RPCA_CASE(8) RPCA_CASE(9) RPCA_CASE(10) RPCA_CASE(11) RPCA_CASE(12)
+        RPCA_CASE(13) RPCA_CASE(14) RPCA_CASE(15) RPCA_CASE(16)
+#undef RPCA_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <bool REBUILD>
+int mx_occupancy_t(int K) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (K) {
+#define RPCA_CASE(KK)                                                                                   \
+    case KK:                                                                                            \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stream_mx<KK, REBUILD>, STREAM_THREADS, 0); \
+        break;
+        RPCA_CASE(1) RPCA_CASE(2) RPCA_CASE(3) RPCA_CASE(4) RPCA_CASE(5) RPCA_CASE(6)
+        RPCA_CASE(7) RPCA_CASE(8) RPCA_CASE(9) RPCA_CASE(10) RPCA_CASE(11) RPCA_CASE(12)
+        RPCA_CASE(13) RPCA_CASE(14) RPCA_CASE(15) RPCA_CASE(16)
+#undef RPCA_CASE
+        default: break;
+    }
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+}  // namespace
+
+int stream_mx_occupancy(int K, bool rebuild) {
+    return rebuild ? mx_occupancy_t<true>(K) : mx_occupancy_t<false>(K);
+}
+
+hipError_t launch_stream_mx(const StreamArgs& a, int K, bool rebuild, hipStream_t s) {
+    return rebuild ? mx_dispatch<true>(a, K, s) : mx_dispatch<false>(a, K, s);
+}
+
+}  // namespace rpca

@@ -26,6 +26,8 @@ LIB_PATH = os.path.join(_HERE, "librpca.so")
 RPCA_OK, RPCA_MAXITER = 0, 1
 RPCA_F64, RPCA_F32 = 0, 1
 RPCA_FLAG_NO_TRIM = 1
+RPCA_FLAG_MIXED = 2
+RPCA_PROF_KINDS = 2
 RPCA_MAX_RANK = 16
 
 EXPORTED = ("rpca_workspace_size", "rpca_init", "rpca_trim", "rpca_step", "rpca_solve",
@@ -49,7 +51,7 @@ class Params(ctypes.Structure):
                 ("mu", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("init_block", ctypes.c_int32),
                 ("init_max_passes", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("mixed_err", ctypes.c_double)]
 
 
 class State(ctypes.Structure):
@@ -176,11 +178,24 @@ def rpca_profile_enable(on: bool) -> None:
     _check(_lib().rpca_profile_enable(1 if on else 0), "rpca_profile_enable")
 
 
-def rpca_profile_read() -> tuple[float, int]:
-    ms = ctypes.c_double(0.0)
-    n = ctypes.c_int64(0)
-    _check(_lib().rpca_profile_read(ctypes.byref(ms), ctypes.byref(n)), "rpca_profile_read")
-    return float(ms.value), int(n.value)
+def rpca_profile_read(kind: int | None = None):
+    """Per kind of streaming pass ([0] dtype of D, [1] BF16 products): summed
+    milliseconds and pass counts since the last read. With kind given, that
+    kind's (ms, count); otherwise the totals over both kinds."""
+    ms = (ctypes.c_double * RPCA_PROF_KINDS)()
+    n = (ctypes.c_int64 * RPCA_PROF_KINDS)()
+    _check(_lib().rpca_profile_read(ms, n), "rpca_profile_read")
+    if kind is None:
+        return float(sum(ms)), int(sum(n))
+    return float(ms[kind]), int(n[kind])
+
+
+def rpca_profile_read_all():
+    """((ms, count) of the dtype passes, (ms, count) of the BF16-product passes)."""
+    ms = (ctypes.c_double * RPCA_PROF_KINDS)()
+    n = (ctypes.c_int64 * RPCA_PROF_KINDS)()
+    _check(_lib().rpca_profile_read(ms, n), "rpca_profile_read")
+    return [(float(ms[k]), int(n[k])) for k in range(RPCA_PROF_KINDS)]
 
 
 # ---- convenience wrapper -----------------------------------------------------
@@ -199,7 +214,7 @@ class SolveInfo:
 
 def make_params(D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: float, mu: float,
                 tol: float = 1e-5, max_iter: int = 100, trim: bool = True, init_block: int = 0,
-                init_max_passes: int = 0, seed: int = 0) -> Params:
+                init_max_passes: int = 0, seed: int = 0, mixed: bool = False, mixed_err: float = 0.0) -> Params:
     if D.dim() != 2 or D.stride(1) != 1:
         raise ValueError("D must be a 2-D row-major tensor with unit column stride")
     if D.dtype == torch.float64:
@@ -211,7 +226,8 @@ def make_params(D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: f
     return Params(m=D.shape[0], n=D.shape[1], ldd=D.stride(0), r=int(r), dtype=dt, beta=float(beta),
                   beta_init=float(beta_init), gamma=float(gamma), mu=float(mu) if trim else 0.0, tol=float(tol),
                   max_iter=int(max_iter), init_block=int(init_block), init_max_passes=int(init_max_passes),
-                  flags=0 if trim else RPCA_FLAG_NO_TRIM, seed=int(seed))
+                  flags=(0 if trim else RPCA_FLAG_NO_TRIM) | (RPCA_FLAG_MIXED if mixed else 0), seed=int(seed),
+                  mixed_err=float(mixed_err))
 
 
 class Solver:
@@ -219,12 +235,12 @@ class Solver:
 
     def __init__(self, D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: float, mu: float,
                  tol: float = 1e-5, max_iter: int = 100, trim: bool = True, init_block: int = 0,
-                 init_max_passes: int = 0, seed: int = 0):
+                 init_max_passes: int = 0, seed: int = 0, mixed: bool = False, mixed_err: float = 0.0):
         if not D.is_cuda:
             raise ValueError("D must be a device tensor")
         self.D = D
         self.params = make_params(D, r, beta, beta_init, gamma, mu, tol, max_iter, trim, init_block,
-                                  init_max_passes, seed)
+                                  init_max_passes, seed, mixed, mixed_err)
         dev = D.device
         m, n = D.shape
         self.U = torch.zeros((m, r), dtype=torch.float64, device=dev)

@@ -33,8 +33,8 @@ def test_header_and_exports_agree(lib):
 
 def test_struct_layout_matches_header(lib):
     # offsets the C compiler uses for the two structs (natural alignment)
-    assert ctypes.sizeof(R.Params) == 8 * 3 + 4 * 2 + 8 * 5 + 4 * 4 + 8
-    assert R.Params.seed.offset == ctypes.sizeof(R.Params) - 8
+    assert ctypes.sizeof(R.Params) == 8 * 3 + 4 * 2 + 8 * 5 + 4 * 4 + 8 + 8
+    assert R.Params.mixed_err.offset == ctypes.sizeof(R.Params) - 8
     assert ctypes.sizeof(R.State) == 8 * 3 + 8 * 5 + 4 * 4
 
 
@@ -59,6 +59,7 @@ def test_workspace_size_and_version(lib):
     dict(beta=0.0), dict(beta_init=-1.0), dict(gamma=1.0), dict(gamma=-0.1), dict(tol=0.0),
     dict(mu=0.0), dict(max_iter=-1), dict(init_block=2), dict(init_block=17), dict(flags=4),
     dict(beta=float("nan")), dict(tol=float("inf")),
+    dict(flags=2, dtype=0), dict(flags=2, dtype=1, mixed_err=float("nan")),
 ])
 def test_invalid_params_rejected(lib, bad):
     with pytest.raises(R.RpcaError) as e:
@@ -68,6 +69,12 @@ def test_invalid_params_rejected(lib, bad):
 
 def test_no_trim_allows_zero_mu(lib):
     assert R.rpca_workspace_size(_params(mu=0.0, flags=R.RPCA_FLAG_NO_TRIM)) > 0
+
+
+def test_mixed_form_needs_fp32(lib):
+    assert R.rpca_workspace_size(_params(dtype=R.RPCA_F32, flags=R.RPCA_FLAG_MIXED)) > 0
+    assert R.rpca_workspace_size(_params(dtype=R.RPCA_F32, flags=R.RPCA_FLAG_MIXED | R.RPCA_FLAG_NO_TRIM,
+                                         mu=0.0, mixed_err=1e-2)) > 0
 
 
 def test_null_pointers_rejected_before_launch(lib):
