@@ -54,9 +54,9 @@ extern "C" {
 
 /* ---- flags ------------------------------------------------------------- */
 #define RPCA_FLAG_NO_TRIM 1u  /* AccAltProj without trim (Section 3): U~ = U_k, V~ = V_k */
-/* Mixed-precision form (RPCA_F32 only): the two tangent products
- * Y1 = (D - S_k) V~ and Y2 = (D - S_k)^T U~ of a loop body run on the matrix
- * cores with BF16 operands and FP32 accumulation; the rebuild of L_k, the
+/* Mixed-precision form (RPCA_F32 only): the tangent product
+ * Y1 = (D - S_k) V~ of a loop body runs on the matrix cores with BF16 operands
+ * and FP32 accumulation; Y2 = (D - S_k)^T U~, the rebuild of L_k, the
  * threshold, the residual and err_k stay FP32, as does all small algebra
  * (FP64). In rpca_solve, body k (which computes err_k and L_{k+1}) takes BF16
  * products while err_j >= mixed_err for every j <= k - 2 (bodies 0 and 1
@@ -155,8 +155,8 @@ int rpca_materialize(const void *D, const rpca_params *p, const rpca_state *st,
  *   Y1 = Z V_t   (device m x r, FP64)    Y2 = Z^T U_t (device n x r, FP64)
  *   *resid2 = sum over |x_ij| <= zeta of x_ij^2   (host scalar),
  * where U_t (m x r) and V_t (n x r) are device FP64 bases. Inputs are rounded
- * to dtype before the pass, as inside rpca_step; with RPCA_FLAG_MIXED the
- * products are the BF16 matrix-core ones. */
+ * to dtype before the pass, as inside rpca_step; with RPCA_FLAG_MIXED, Y1 is
+ * the BF16 matrix-core product. */
 int rpca_tangent_products(const void *D, const rpca_params *p,
                           const double *A_L, const double *B_L, double zeta,
                           const double *U_t, const double *V_t,
@@ -170,7 +170,7 @@ int rpca_tangent_products(const void *D, const rpca_params *p,
  * waits for the recorded passes and returns, per kind of pass, their summed
  * duration in ms and their number since the previous read, then resets them:
  * stream_ms and stream_launches are arrays of RPCA_PROF_KINDS entries, [0] the
- * passes in the dtype of D, [1] the passes with BF16 products. Disabling keeps
+ * passes in the dtype of D, [1] the passes with the BF16 product. Disabling keeps
  * the totals for a final read. Intended for benchmarks: the events add a few
  * microseconds of queue work per pass. */
 #define RPCA_PROF_KINDS 2

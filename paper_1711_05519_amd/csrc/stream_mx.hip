@@ -1,24 +1,23 @@
-// The streaming pass with the two tangent products on the matrix cores (the
-// mixed-precision form). Per element of D, in FP32 on the vector ALUs: the
-// rank-K rebuild of L, the threshold T_zeta, the residual (Section 2.1 and
-// Algorithm 1), exactly as in the FP32 pass. The thresholded tile Z = D - S is
-// then rounded to BF16 into LDS and both products
-//   Y1 = Z V_f  (m x K),   Y2 = Z^T U_f  (n x K)
-// run as v_mfma_f32_16x16x32_bf16 with FP32 accumulation; U_f and V_f are
-// rounded to BF16 as well. Only the products lose precision (BF16 operands,
-// relative error ~2^-9 per term); the threshold decisions, the residual and
-// err_k are the FP32 ones. The library switches to the FP32 pass once err_k
-// falls below a set level, so the final iterate is the FP32 method's.
+// The streaming pass with the product Y1 = Z V_f on the matrix cores (the
+// mixed-precision form). Per element of D, in FP32 on the vector ALUs, as in
+// the FP32 pass: the rank-K rebuild of L, the threshold T_zeta, the residual
+// (Section 2.1 and Algorithm 1), and the column product Y2 = Z^T U_f, which
+// each lane accumulates over rows for its own four columns. Y1 needs the sum
+// over columns, which on the vector ALUs costs a cross-lane reduction per row;
+// here the thresholded rows of Z are rounded to BF16 into LDS and Y1 runs as
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation (V_f rounded to BF16 too).
+// Only Y1 loses precision (BF16 operands, ~2^-9 relative per term); the
+// threshold decisions, the residual, err_k and Y2 are the FP32 ones. The
+// library switches to the FP32 pass once err_k falls below a set level.
 //
 // Layout: workgroup of 4 waves, tile TM rows x 256 columns; each wave takes
-// blocks of 32 rows (rows i0 + 32w, i0 + 32(w + 4), ...). Phase A: the lane
-// owns columns 4l..4l+3 of the tile, 4 rows per batch of loads, and writes the
-// BF16 values of Z row-major into its wave's LDS block (row pitch 260 BF16:
-// the pad spreads the column reads over the banks). Phase B: Y1 of the two
-// 16-row halves from row reads (8 consecutive columns per lane, the MFMA A
-// layout), Y2 of the sixteen 16-column blocks from column reads (8 consecutive
-// rows per lane). MFMA 16x16x32 lane layout: A row l%16, k = 8(l/16)+q;
-// B column l%16, k = 8(l/16)+q; C column l%16, rows 4(l/16)+r.
+// blocks of 16 rows (rows i0 + 16w, i0 + 16(w + 4), ...). Phase A: the lane
+// owns columns 4l..4l+3, loads MX_BATCH rows at a time (the next batch in
+// flight), and writes BF16 Z row-major into its wave's LDS block (row pitch
+// 260 BF16: the pad spreads the row reads over the banks). Phase B: Y1 of the
+// 16 rows, eight MFMAs over the 32-column blocks of the tile, A read from LDS
+// (8 consecutive columns per lane). MFMA 16x16x32 lane layout: A row l%16,
+// k = 8(l/16)+q; B column l%16, k = 8(l/16)+q; C column l%16, rows 4(l/16)+r.
 // Partials are written in the FP32 pass's layout, so the gather is shared.
 
 #include "launch.hpp"
@@ -29,7 +28,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int MX_RB = 32;                 // rows per wave block
+constexpr int MX_RB = 16;                 // rows per wave block (MFMA M)
 constexpr int MX_PITCH = STREAM_TN + 4;   // BF16 per LDS row
 constexpr int MX_BATCH = 4;               // rows per batch of loads in phase A
 
@@ -70,17 +69,21 @@ __device__ inline void mx_load_batch(const float* __restrict__ D, int64_t ldd, i
     }
 }
 
-// Threshold and residual of one batch; Z in BF16 into the wave's LDS block.
+// Threshold, residual and Y2 of one batch; Z in BF16 into the wave's LDS block.
 template <int K, bool REBUILD>
-__device__ inline void mx_compute_batch(const float (&d)[MX_BATCH][4], const float* __restrict__ AL, int i0, int i_hi,
-                                        int r_local, float zeta, const float (&bl)[4][K], uint16_t* zl, int lane,
+__device__ inline void mx_compute_batch(const float (&d)[MX_BATCH][4], const float* __restrict__ AL,
+                                        const float* __restrict__ Uf, int i0, int i_hi, int r_local, float zeta,
+                                        const float (&bl)[4][K], float (&y2)[4][K], uint16_t* zl, int lane,
                                         float& rs, float& amax) {
 #pragma unroll
     for (int b = 0; b < MX_BATCH; ++b) {
         const int i = i0 + b;
-        float al[K];
+        float al[K], ut[K];
 #pragma unroll
-        for (int t = 0; t < K; ++t) al[t] = (REBUILD && i < i_hi) ? AL[(size_t)i * K + t] : 0.f;
+        for (int t = 0; t < K; ++t) {
+            al[t] = (REBUILD && i < i_hi) ? AL[(size_t)i * K + t] : 0.f;
+            ut[t] = i < i_hi ? Uf[(size_t)i * K + t] : 0.f;
+        }
         float z[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -96,6 +99,8 @@ __device__ inline void mx_compute_batch(const float (&d)[MX_BATCH][4], const flo
             const float e = big ? 0.f : x;
             rs = fmaf(e, e, rs);
             z[s] = big ? dv - x : dv;
+#pragma unroll
+            for (int t = 0; t < K; ++t) y2[s][t] = fmaf(z[s], ut[t], y2[s][t]);
         }
         uint2 w;
         w.x = pack2(z[0], z[1]);
@@ -108,9 +113,10 @@ template <int K, bool REBUILD, bool FULL>
 __device__ inline void mx_tile(const float* __restrict__ D, const float* __restrict__ AL,
                                const float* __restrict__ Uf, float* __restrict__ P1, const StreamGeom& g, float zeta,
                                int ct, int i_lo, int i_hi, int wave, int lane, int jb, int nvalid,
-                               const float (&bl)[4][K], const bf16x8* vl, uint16_t* zl, f32x4 (&acc2)[STREAM_TN / 16],
+                               const float (&bl)[4][K], float (&y2)[4][K], const bf16x8* vl, uint16_t* zl,
                                double& res, float& amax) {
     const int lr = lane & 15, lg = lane >> 4;
+    const bf16x8 zero8 = {};
     float ba[MX_BATCH][4], bb[MX_BATCH][4];
     int i0 = i_lo + MX_RB * wave;
     if (i0 < i_hi) mx_load_batch<FULL>(D, g.ldd, i0, i_hi, jb, nvalid, ba);
@@ -118,68 +124,39 @@ __device__ inline void mx_tile(const float* __restrict__ D, const float* __restr
         float rs = 0.f;
         // phase A: batches of MX_BATCH rows in two register buffers; the loads
         // of the next batch (or of the next block's first batch) are in flight
-        // while one is computed
+        // while one is computed. Rows at or past i_hi load as zeros.
         const int i_next = i0 + MX_RB * STREAM_WAVES;
 #pragma unroll 1
         for (int bt = 0; bt < MX_RB / MX_BATCH; bt += 2) {
             mx_load_batch<FULL>(D, g.ldd, i0 + MX_BATCH * (bt + 1), i_hi, jb, nvalid, bb);
-            mx_compute_batch<K, REBUILD>(ba, AL, i0 + MX_BATCH * bt, i_hi, MX_BATCH * bt, zeta, bl, zl, lane, rs,
-                                         amax);
-            // rows at or past i_hi load as zeros: a partial block computes zeros
+            mx_compute_batch<K, REBUILD>(ba, AL, Uf, i0 + MX_BATCH * bt, i_hi, MX_BATCH * bt, zeta, bl, y2, zl, lane,
+                                         rs, amax);
             const int inx = (bt + 2 < MX_RB / MX_BATCH) ? i0 + MX_BATCH * (bt + 2) : i_next;
             mx_load_batch<FULL>(D, g.ldd, inx, i_hi, jb, nvalid, ba);
-            mx_compute_batch<K, REBUILD>(bb, AL, i0 + MX_BATCH * (bt + 1), i_hi, MX_BATCH * (bt + 1), zeta, bl, zl,
-                                         lane, rs, amax);
+            mx_compute_batch<K, REBUILD>(bb, AL, Uf, i0 + MX_BATCH * (bt + 1), i_hi, MX_BATCH * (bt + 1), zeta, bl,
+                                         y2, zl, lane, rs, amax);
         }
         res += static_cast<double>(rs);
         mx_wave_sync();
 
-        // phase B, Y1: rows i0 + 16h + lr, columns 32kb + 8lg + q
+        // phase B, Y1: rows i0 + lr, columns 32kb + 8lg + q
+        f32x4 a1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            f32x4 a1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kb = 0; kb < STREAM_TN / 32; ++kb) {
-                const uint16_t* src = zl + (16 * h + lr) * MX_PITCH + 32 * kb + 8 * lg;
-                const uint2 w0 = *reinterpret_cast<const uint2*>(src);
-                const uint2 w1 = *reinterpret_cast<const uint2*>(src + 4);
-                bf16x8 A;
-                A[0] = __builtin_bit_cast(__bf16, (uint16_t)(w0.x & 0xffff));
-                A[1] = __builtin_bit_cast(__bf16, (uint16_t)(w0.x >> 16));
-                A[2] = __builtin_bit_cast(__bf16, (uint16_t)(w0.y & 0xffff));
-                A[3] = __builtin_bit_cast(__bf16, (uint16_t)(w0.y >> 16));
-                A[4] = __builtin_bit_cast(__bf16, (uint16_t)(w1.x & 0xffff));
-                A[5] = __builtin_bit_cast(__bf16, (uint16_t)(w1.x >> 16));
-                A[6] = __builtin_bit_cast(__bf16, (uint16_t)(w1.y & 0xffff));
-                A[7] = __builtin_bit_cast(__bf16, (uint16_t)(w1.y >> 16));
-                a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, vl[kb * WAVE + lane], a1, 0, 0, 0);
-                if ((kb & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-            }
-            if (lr < K) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = i0 + 16 * h + 4 * lg + r;
-                    if (i < i_hi) P1[((size_t)ct * g.m + i) * K + lr] = a1[r];
-                }
-            }
+        for (int kb = 0; kb < STREAM_TN / 32; ++kb) {
+            const uint16_t* src = zl + lr * MX_PITCH + 32 * kb + 8 * lg;
+            const uint2 w0 = *reinterpret_cast<const uint2*>(src);
+            const uint2 w1 = *reinterpret_cast<const uint2*>(src + 4);
+            const uint32_t wv[4] = {w0.x, w0.y, w1.x, w1.y};
+            bf16x8 A = __builtin_bit_cast(bf16x8, wv);
+            const bf16x8 B = lr < K ? vl[(kb * 4 + lg) * K + lr] : zero8;
+            a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, a1, 0, 0, 0);
         }
-        // phase B, Y2: B operand U_f rows i0 + 8lg + q, column lr
-        bf16x8 uB;
+        if (lr < K) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int i = i0 + 8 * lg + q;
-            uB[q] = to_bf16((lr < K && i < i_hi) ? Uf[(size_t)i * K + lr] : 0.f);
-        }
-        // groups of 4 column blocks: the scheduling barrier keeps the reads of
-        // a group next to its MFMAs (hoisting all 128 reads costs occupancy)
-#pragma unroll
-        for (int cb = 0; cb < STREAM_TN / 16; ++cb) {
-            bf16x8 A;
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                A[q] = __builtin_bit_cast(__bf16, zl[(8 * lg + q) * MX_PITCH + 16 * cb + lr]);
-            acc2[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, uB, acc2[cb], 0, 0, 0);
-            if ((cb & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + 4 * lg + r;
+                if (i < i_hi) P1[((size_t)ct * g.m + i) * K + lr] = a1[r];
+            }
         }
         mx_wave_sync();
     }
@@ -202,57 +179,55 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream_mx(
     const int nvalid = min(max(g.n - jb, 0), 4);
     const int i_lo = rt * g.TM;
     const int i_hi = min(g.m, i_lo + g.TM);
-    const int lr = lane & 15, lg = lane >> 4;   // MFMA row/column index and k group
 
     __shared__ uint16_t zbuf[STREAM_WAVES][MX_RB * MX_PITCH];
     __shared__ double red[STREAM_WAVES];
     uint16_t* zl = zbuf[wave];
-    // B operands of Y1 in LDS, one 16-byte vector per (32-column block, lane):
-    // V_f rows c0 + 32kb + 8lg + q, column lr (zero when lr >= K)
-    __shared__ bf16x8 vl[(STREAM_TN / 32) * WAVE];
-    for (int e = threadIdx.x; e < (STREAM_TN / 32) * WAVE; e += STREAM_THREADS) {
-        const int kb = e / WAVE, ln = e % WAVE;
-        const int t = ln & 15, grp = ln >> 4;
+    // B operands of Y1 in LDS: for (32-column block kb, k group lg, column t
+    // < K) the 8 BF16 values V_f[c0 + 32kb + 8lg + q][t]
+    __shared__ bf16x8 vl[(STREAM_TN / 32) * 4 * K];
+    for (int e = threadIdx.x; e < (STREAM_TN / 32) * 4 * K; e += STREAM_THREADS) {
+        const int t = e % K, grp = (e / K) % 4, kb = e / (4 * K);
         bf16x8 v;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int j = c0 + 32 * kb + 8 * grp + q;
-            v[q] = to_bf16((t < K && j < g.n) ? Vf[(size_t)j * K + t] : 0.f);
+            v[q] = to_bf16(j < g.n ? Vf[(size_t)j * K + t] : 0.f);
         }
         vl[e] = v;
     }
     __syncthreads();
 
-    float bl[4][K];
+    float bl[4][K], y2[4][K];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int t = 0; t < K; ++t) bl[s][t] = (REBUILD && s < nvalid) ? BL[(size_t)(jb + s) * K + t] : 0.f;
-    f32x4 acc2[STREAM_TN / 16];
-#pragma unroll
-    for (int cb = 0; cb < STREAM_TN / 16; ++cb) acc2[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < K; ++t) {
+            bl[s][t] = (REBUILD && s < nvalid) ? BL[(size_t)(jb + s) * K + t] : 0.f;
+            y2[s][t] = 0.f;
+        }
     double res = 0.0;
     float amax = 0.f;
     const bool full = g.vec_ok && c0 + STREAM_TN <= g.n;   // uniform per workgroup
     if (full)
-        mx_tile<K, REBUILD, true>(D, AL, Uf, P1, g, zeta, ct, i_lo, i_hi, wave, lane, jb, nvalid, bl, vl, zl, acc2,
+        mx_tile<K, REBUILD, true>(D, AL, Uf, P1, g, zeta, ct, i_lo, i_hi, wave, lane, jb, nvalid, bl, y2, vl, zl,
                                   res, amax);
     else
-        mx_tile<K, REBUILD, false>(D, AL, Uf, P1, g, zeta, ct, i_lo, i_hi, wave, lane, jb, nvalid, bl, vl, zl, acc2,
+        mx_tile<K, REBUILD, false>(D, AL, Uf, P1, g, zeta, ct, i_lo, i_hi, wave, lane, jb, nvalid, bl, y2, vl, zl,
                                    res, amax);
 
-    // Y2 partial of the tile: sum of the four waves through LDS (fixed order),
-    // lane holds columns 16cb + 4lg + r, column lr of Y2
+    // Y2 partial of the tile: sum of the four waves' column partials through
+    // LDS (fixed order)
     __syncthreads();
     float* sm = reinterpret_cast<float*>(&zbuf[0][0]);   // STREAM_TN * K floats
     for (int w = 0; w < STREAM_WAVES; ++w) {
-        if (wave == w && lr < K) {
+        if (wave == w) {
 #pragma unroll
-            for (int cb = 0; cb < STREAM_TN / 16; ++cb)
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int idx = (16 * cb + 4 * lg + r) * K + lr;
-                    sm[idx] = (w == 0) ? acc2[cb][r] : sm[idx] + acc2[cb][r];
+                for (int t = 0; t < K; ++t) {
+                    const int idx = (lane * 4 + s) * K + t;
+                    sm[idx] = (w == 0) ? y2[s][t] : sm[idx] + y2[s][t];
                 }
         }
         __syncthreads();

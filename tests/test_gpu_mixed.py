@@ -1,11 +1,12 @@
-"""Mixed-precision form (RPCA_FLAG_MIXED): the two tangent products on the
-matrix cores with BF16 operands and FP32 accumulation, everything else FP32 /
-FP64 as in the FP32 path.
+"""Mixed-precision form (RPCA_FLAG_MIXED): the row product Y1 = Z V_f on the
+matrix cores with BF16 operands and FP32 accumulation; the column product
+Y2 = Z^T U_f, the threshold and the residual in FP32, small algebra in FP64,
+as in the FP32 path.
 
 Parity unpinned by the paper (a precision choice of this implementation).
-Pins used instead: the products against an FP64 reference computed from the
-BF16-rounded operands (the kernel's own rounding, so element-level agreement
-up to FP32 accumulation is required), the threshold residual against the FP64
+Pins used instead: Y1 against an FP64 reference computed from the
+BF16-rounded operands (the kernel's own rounding, so agreement up to FP32
+accumulation is required), Y2 and the threshold residual against the FP64
 oracle at the FP32 tolerance, and whole solves against the FP64 oracle and the
 ground truth at the 1e-4 level of the paper's success criterion (Section 4).
 """
@@ -63,9 +64,9 @@ def test_mixed_tangent_products(m, n, r):
     S = np.where(np.abs(x) > zeta, x, 0.0)
     Z = D - S
     res_o = float(np.sum(np.where(np.abs(x) <= zeta, x * x, 0.0)))
-    # the kernel's operands: Z, U_t, V_t rounded to BF16
-    Zb, Ub, Vb = bf16(Z), bf16(Ut), bf16(Vt)
-    Y1b, Y2b = Zb @ Vb, Zb.T @ Ub
+    # the operands of the Y1 product: Z and V_t rounded to BF16
+    Zb, Vb = bf16(Z), bf16(Vt)
+    Y1b = Zb @ Vb
     Y1o, Y2o = Z @ Vt, Z.T @ Ut
     sv = R.Solver(dev(D, torch.float32), r, 0.01, 0.02, 0.5, 1.0, mixed=True)
     Y1, Y2, res = sv.tangent_products(dev(A), dev(B), zeta, dev(Ut), dev(Vt))
@@ -73,9 +74,10 @@ def test_mixed_tangent_products(m, n, r):
     # FP32 rebuild of L can move a value of Z across a BF16 rounding boundary:
     # a few one-ulp differences of the operands, hence 1e-4 rather than FP32 eps
     assert rel(Y1, Y1b) < 1e-4, rel(Y1, Y1b)
-    assert rel(Y2, Y2b) < 1e-4, rel(Y2, Y2b)
-    # and the BF16 products are products to BF16 accuracy
-    assert rel(Y1, Y1o) < 2e-2 and rel(Y2, Y2o) < 2e-2
+    # and the BF16 product is the exact product to BF16 accuracy
+    assert rel(Y1, Y1o) < 2e-2
+    # Y2 and the residual are the FP32 path's
+    assert rel(Y2, Y2o) < 2e-6, rel(Y2, Y2o)
     assert abs(res - res_o) / res_o < 2e-6
 
 
