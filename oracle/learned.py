@@ -1,0 +1,179 @@
+"""FP64 CPU references for the learned-threshold extension (test infrastructure).
+
+Not part of the paper: the paper fixes the threshold schedule
+zeta_{k+1} = beta (sigma_{r+1} + gamma^{k+1} sigma_1) (Algorithm 1, Section 2.1).
+This module is the plain reference for two additions built on top of it:
+
+* a small multilayer perceptron that maps features of the current iterate to a
+  threshold zeta_k (4 -> 32 -> 32 -> 1, ReLU hidden layers, softplus output
+  scaled by beta * sigma_1), its gradient and one Adam update (Kingma and Ba,
+  "Adam: a method for stochastic optimization", Algorithm 1);
+* one AccAltProj iteration with the hard threshold T_zeta replaced by the
+  relaxation s(x) = x * logistic((|x| - zeta) / tau), which tends to T_zeta as
+  tau -> 0, together with the derivative of a loss of the next iterate with
+  respect to zeta.
+
+Everything is dense float64 and literal: the derivative of the rank-r
+truncation H_r is the first-order perturbation of a full dense SVD, written
+out below. Parity of these functions is not pinned by the paper (it has no
+learned threshold); the tests pin them by central finite differences, closed
+forms and limits instead.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import accaltproj as A
+
+# ---------------------------------------------------------------- the MLP ----
+
+N_IN, N_H = 4, 32
+# flat parameter layout: W1 (32x4, row-major), b1 (32), W2 (32x32), b2 (32), w3 (32), b3 (1)
+SIZES = (N_H * N_IN, N_H, N_H * N_H, N_H, N_H, 1)
+N_PARAMS = sum(SIZES)          # 1249
+FEATURE_FLOOR = 1e-30          # floor inside the logarithms of the features
+
+
+def unpack(theta: np.ndarray):
+    theta = np.asarray(theta, dtype=np.float64)
+    assert theta.shape == (N_PARAMS,)
+    out, o = [], 0
+    for sz in SIZES:
+        out.append(theta[o:o + sz])
+        o += sz
+    W1, b1, W2, b2, w3, b3 = out
+    return W1.reshape(N_H, N_IN), b1, W2.reshape(N_H, N_H), b2, w3, b3[0]
+
+
+def features(k: int, K: int, sigma1: float, sigma_r1: float, err: float, normD: float) -> np.ndarray:
+    """phi_k = (k / K, log(sigma_{r+1} / sigma_1), log err_k, log(sigma_1 / ||D||_F))."""
+    f = FEATURE_FLOOR
+    return np.array([k / K,
+                     np.log(max(sigma_r1, f) / max(sigma1, f)),
+                     np.log(max(err, f)),
+                     np.log(max(sigma1, f) / max(normD, f))], dtype=np.float64)
+
+
+def softplus(o: float) -> float:
+    return float(np.logaddexp(0.0, o))
+
+
+def mlp_forward(theta: np.ndarray, phi: np.ndarray):
+    """Returns (o, cache): o = w3 . relu(W2 relu(W1 phi + b1) + b2) + b3."""
+    W1, b1, W2, b2, w3, b3 = unpack(theta)
+    a1 = W1 @ phi + b1
+    h1 = np.maximum(a1, 0.0)
+    a2 = W2 @ h1 + b2
+    h2 = np.maximum(a2, 0.0)
+    o = float(w3 @ h2 + b3)
+    return o, (phi, a1, h1, a2, h2)
+
+
+def zeta_of(o: float, beta: float, sigma1: float) -> float:
+    """zeta = beta * sigma_1 * softplus(o)."""
+    return beta * sigma1 * softplus(o)
+
+
+def mlp_backward(theta: np.ndarray, cache, grad_o: float) -> np.ndarray:
+    """d(grad_o * o)/d theta, flat, by the chain rule through the two ReLU layers."""
+    W1, b1, W2, b2, w3, b3 = unpack(theta)
+    phi, a1, h1, a2, h2 = cache
+    g_w3 = grad_o * h2
+    g_b3 = grad_o
+    g_h2 = grad_o * w3
+    g_a2 = g_h2 * (a2 > 0)
+    g_W2 = np.outer(g_a2, h1)
+    g_b2 = g_a2
+    g_h1 = W2.T @ g_a2
+    g_a1 = g_h1 * (a1 > 0)
+    g_W1 = np.outer(g_a1, phi)
+    g_b1 = g_a1
+    return np.concatenate([g_W1.ravel(), g_b1, g_W2.ravel(), g_b2, g_w3, [g_b3]])
+
+
+def adam_step(theta, m, v, g, t: int, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    """One Adam update (t counts from 1); returns new (theta, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mhat = m / (1.0 - b1 ** t)
+    vhat = v / (1.0 - b2 ** t)
+    return theta - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def init_theta(seed: int) -> np.ndarray:
+    """He-style normal weights, zero biases, and b3 = log(e - 1) so that the
+    untrained output is softplus(b3) = 1, i.e. zeta = beta * sigma_1."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal((N_H, N_IN)) * np.sqrt(2.0 / N_IN)
+    W2 = rng.standard_normal((N_H, N_H)) * np.sqrt(2.0 / N_H)
+    w3 = rng.standard_normal(N_H) * np.sqrt(1.0 / N_H) * 0.1
+    return np.concatenate([W1.ravel(), np.zeros(N_H), W2.ravel(), np.zeros(N_H), w3, [np.log(np.e - 1.0)]])
+
+
+# ------------------------------------------------ relaxed iteration ---------
+
+def logistic(u):
+    return 0.5 * (1.0 + np.tanh(0.5 * u))
+
+
+def soft_threshold(x: np.ndarray, zeta: float, tau: float) -> np.ndarray:
+    """s(x) = x * logistic((|x| - zeta) / tau); T_zeta(x) in the limit tau -> 0."""
+    return x * logistic((np.abs(x) - zeta) / tau)
+
+
+def soft_threshold_dzeta(x: np.ndarray, zeta: float, tau: float) -> np.ndarray:
+    """d s / d zeta = -x * logistic'(u) / tau, u = (|x| - zeta) / tau."""
+    g = logistic((np.abs(x) - zeta) / tau)
+    return -x * g * (1.0 - g) / tau
+
+
+def relaxed_step(D: np.ndarray, st: A.State, zeta: float, tau: float, p: A.Params):
+    """One iteration of Algorithm 1 from L_k = st.L() with the relaxed threshold:
+    Z = D - s(D - L_k); L_{k+1} = H_r(P_T(Z)) with T from Trim(L_k).
+    Returns (L_{k+1}, P_T(Z), Ut, Vt)."""
+    Ut, Vt = A.trimmed_bases(st.U, st.V, p.mu, p.r)
+    X = D - st.L()
+    Z = D - soft_threshold(X, zeta, tau)
+    PZ = A.tangent_projection(Ut, Vt, Z)
+    U, s, V = A.best_rank_r(PZ, p.r)
+    return (U * s) @ V.T, PZ, Ut, Vt
+
+
+def step_loss(D, st, zeta, tau, p, L_true) -> float:
+    """||L_{k+1} - L_true||_F^2 / ||L_true||_F^2 after one relaxed iteration."""
+    L1, _, _, _ = relaxed_step(D, st, zeta, tau, p)
+    return float(np.sum((L1 - L_true) ** 2) / np.sum(L_true ** 2))
+
+
+def truncation_derivative(Amat: np.ndarray, E: np.ndarray, r: int) -> np.ndarray:
+    """First-order change of H_r(Amat) in the direction E, from the full SVD
+    Amat = U diag(s) V^T: with F = U^T E V, the change is U G V^T where
+    G_ij = F_ij for i, j < r; for i < r <= j (s_j = 0 past min(m, n)),
+    G_ij = (s_i^2 F_ij + s_i s_j F_ji) / (s_i^2 - s_j^2) and
+    G_ji = (s_i^2 F_ji + s_i s_j F_ij) / (s_i^2 - s_j^2); G_ij = 0 for i, j >= r.
+    (Requires s_{r-1} > s_r.)"""
+    m, n = Amat.shape
+    U, s, Vt = np.linalg.svd(Amat, full_matrices=True)
+    V = Vt.T
+    sf = np.zeros(max(m, n))
+    sf[:len(s)] = s
+    F = U.T @ E @ V
+    G = np.zeros_like(F)
+    G[:r, :r] = F[:r, :r]
+    for i in range(r):
+        for j in range(r, n):
+            G[i, j] = (sf[i] ** 2 * F[i, j] + sf[i] * sf[j] * (F[j, i] if j < m else 0.0)) / (sf[i] ** 2 - sf[j] ** 2)
+        for j in range(r, m):
+            G[j, i] = (sf[i] ** 2 * F[j, i] + sf[i] * sf[j] * (F[i, j] if j < n else 0.0)) / (sf[i] ** 2 - sf[j] ** 2)
+    return U @ G @ V.T
+
+
+def step_loss_grad_zeta(D, st, zeta, tau, p, L_true) -> float:
+    """d step_loss / d zeta: Z depends on zeta through s, P_T is linear, and
+    H_r changes by truncation_derivative in the direction P_T(dZ/dzeta)."""
+    L1, PZ, Ut, Vt = relaxed_step(D, st, zeta, tau, p)
+    X = D - st.L()
+    dZ = -soft_threshold_dzeta(X, zeta, tau)
+    dPZ = A.tangent_projection(Ut, Vt, dZ)
+    dL1 = truncation_derivative(PZ, dPZ, p.r)
+    return float(2.0 * np.sum((L1 - L_true) * dL1) / np.sum(L_true ** 2))

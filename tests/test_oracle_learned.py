@@ -1,0 +1,116 @@
+"""Pins of the FP64 reference for the learned-threshold extension (CPU only).
+
+The paper has no learned threshold, so these references are pinned by
+mathematics instead: central finite differences of every derivative, closed
+forms (an Adam step at t = 1, the untrained output), and limits (the relaxed
+threshold tends to T_zeta as tau -> 0, the relaxed iteration to Algorithm 1).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import learned as Lr
+from paper_1711_05519_amd import inputs as I
+
+
+def test_mlp_layout_and_untrained_output():
+    assert Lr.N_PARAMS == 1249
+    th = Lr.init_theta(0)
+    # zero first-layer weights give o = b3 exactly; init b3 makes softplus(o) = 1
+    z = th.copy()
+    z[:Lr.N_H * Lr.N_IN] = 0.0
+    z[Lr.N_H * Lr.N_IN:Lr.N_H * Lr.N_IN + Lr.N_H] = 0.0
+    o, _ = Lr.mlp_forward(z, np.array([0.3, -2.0, -1.0, -4.0]))
+    assert o == pytest.approx(np.log(np.e - 1.0), abs=1e-15)
+    assert Lr.zeta_of(o, 0.01, 1000.0) == pytest.approx(10.0, rel=1e-14)
+
+
+def test_mlp_backward_matches_central_differences():
+    rng = np.random.default_rng(1)
+    th = Lr.init_theta(3) + 0.05 * rng.standard_normal(Lr.N_PARAMS)
+    phi = np.array([0.2, -1.5, -2.5, -3.0])
+    o, cache = Lr.mlp_forward(th, phi)
+    g = Lr.mlp_backward(th, cache, 1.0)
+    h = 1e-6
+    for i in rng.choice(Lr.N_PARAMS, 60, replace=False).tolist() + [Lr.N_PARAMS - 1]:
+        e = np.zeros_like(th)
+        e[i] = h
+        fd = (Lr.mlp_forward(th + e, phi)[0] - Lr.mlp_forward(th - e, phi)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, abs=1e-7, rel=1e-6), i
+
+
+def test_adam_first_step_closed_form():
+    th = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 0.0])
+    th1, m, v = Lr.adam_step(th, np.zeros(3), np.zeros(3), g, 1, lr=0.1, eps=1e-8)
+    # at t = 1 the bias-corrected moments are g and g^2
+    assert np.allclose(th1, th - 0.1 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_features():
+    f = Lr.features(3, 15, sigma1=100.0, sigma_r1=1.0, err=1e-2, normD=1e4)
+    assert np.allclose(f, [0.2, np.log(0.01), np.log(1e-2), np.log(0.01)])
+    assert np.isfinite(Lr.features(0, 15, 1.0, 0.0, 0.0, 1.0)).all()
+
+
+def test_soft_threshold_limit_and_derivative():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(2000) * 3
+    zeta = 2.0
+    far = np.abs(np.abs(x) - zeta) > 0.05
+    s = Lr.soft_threshold(x, zeta, 1e-4)
+    assert np.array_equal(s[far], O.hard_threshold(x, zeta)[far])
+    tau, h = 0.3, 1e-6
+    fd = (Lr.soft_threshold(x, zeta + h, tau) - Lr.soft_threshold(x, zeta - h, tau)) / (2 * h)
+    assert np.allclose(Lr.soft_threshold_dzeta(x, zeta, tau), fd, rtol=1e-6, atol=1e-8)
+
+
+def test_truncation_derivative_matches_central_differences():
+    rng = np.random.default_rng(4)
+    m, n, r = 12, 9, 3
+    U, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.array([9.0, 7.0, 5.0, 2.0, 1.5, 1.0, 0.7, 0.4, 0.1])
+    Amat = (U[:, :n] * s) @ V.T
+    E = rng.standard_normal((m, n))
+    h = 1e-6
+
+    def Hr(X):
+        a, b, c = O.best_rank_r(X, r)
+        return (a * b) @ c.T
+    fd = (Hr(Amat + h * E) - Hr(Amat - h * E)) / (2 * h)
+    an = Lr.truncation_derivative(Amat, E, r)
+    assert np.abs(an - fd).max() < 1e-7 * np.abs(fd).max()
+
+
+def _tiny_case(seed=5):
+    x = I.gaussian_instance(30, 30, 2, 0.1, 1.0, seed=seed)
+    p = O.Params(r=2, beta=x.beta, beta_init=x.beta_init, gamma=x.gamma, mu=x.mu_in, tol=1e-6)
+    D = x.D
+    st = O.initialize(D, p)
+    st = O.step(D, st, p)
+    return x, p, D, st
+
+
+def test_step_loss_grad_zeta_matches_central_differences():
+    x, p, D, st = _tiny_case()
+    L_true = x.L
+    for zeta_scale, tau_scale in [(1.0, 0.05), (0.6, 0.2), (1.5, 0.02)]:
+        zeta = st.zeta * zeta_scale
+        tau = zeta * tau_scale
+        g = Lr.step_loss_grad_zeta(D, st, zeta, tau, p, L_true)
+        h = 1e-6 * zeta
+        fd = (Lr.step_loss(D, st, zeta + h, tau, p, L_true) - Lr.step_loss(D, st, zeta - h, tau, p, L_true)) / (2 * h)
+        assert g == pytest.approx(fd, rel=2e-5, abs=1e-12), (zeta_scale, tau_scale, g, fd)
+
+
+def test_relaxed_step_tends_to_algorithm_1():
+    x, p, D, st = _tiny_case(6)
+    nxt = O.step(D, st, p)
+    # zeta strictly between entries of |D - L_k|: the relaxation with a tiny tau
+    # reproduces the hard-threshold iteration
+    L1, _, _, _ = Lr.relaxed_step(D, st, st.zeta, 1e-9 * st.zeta, p)
+    a = np.abs(D - st.L()).ravel()
+    assert np.min(np.abs(a - st.zeta)) > 1e-6 * st.zeta
+    assert np.abs(L1 - nxt.L()).max() < 1e-9 * np.abs(nxt.L()).max()
