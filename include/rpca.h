@@ -64,6 +64,8 @@ extern "C" {
  * one. rpca_step takes BF16 products while the state's err >= mixed_err (or
  * is unknown). Not part of the paper: a precision choice of this library. */
 #define RPCA_FLAG_MIXED 2u
+/* Workspace for rpca_relaxed_step (threshold training; r <= 10). */
+#define RPCA_FLAG_TRAINING 4u
 
 /* Largest supported rank r and init block p. */
 #define RPCA_MAX_RANK 16
@@ -162,6 +164,30 @@ int rpca_tangent_products(const void *D, const rpca_params *p,
                           const double *U_t, const double *V_t,
                           double *Y1, double *Y2, double *resid2,
                           void *ws, size_t ws_bytes, void *stream);
+
+/* One iteration with a relaxed threshold, for training a learned threshold
+ * schedule (not part of the paper). From the state L_k = U diag(sigma) V^T
+ * (read), with x = D - L_k and s(x) = x * logistic((|x| - zeta) / tau), which
+ * tends to the hard threshold T_zeta of Section 2.1 as tau -> 0:
+ *   Z = D - s(x),  L_{k+1} = H_r(P_T(Z))   (T the tangent space of Trim(L_k))
+ * is written back to the state (U, sigma, V; k += 1; zeta = the given zeta;
+ * err = ||x - s(x)||_F / ||D||_F of L_k; sigma1_pt / sigma_r1_pt = sigma_1 and
+ * sigma_{r+1} of P_T(Z)). For target factors P (device m x r_true) and Q
+ * (device n x r_true), FP64, row stride r_true, out receives
+ *   loss = ||L_{k+1} - P Q^T||_F^2 / ||P Q^T||_F^2  and  d loss / d zeta,
+ * the exact derivative of the relaxed iteration (first-order perturbation of
+ * H_r in a 3r-dimensional reduced space; needs sigma_r > sigma_{r+1}).
+ * Requires RPCA_FLAG_TRAINING in p->flags (workspace), r <= 10,
+ * 1 <= r_true <= 16, zeta > 0, tau > 0. */
+typedef struct {
+    double  loss, dloss_dzeta;
+    double  err;                /* relaxed err_k of the input state                   */
+    double  sigma1, sigma_r1;   /* sigma_1, sigma_{r+1} of P_T(Z)                     */
+    int32_t svd_sweeps, reserved;
+} rpca_relax_result;
+int rpca_relaxed_step(const void *D, const rpca_params *p, rpca_state *st, double zeta, double tau,
+                      const double *P_true, const double *Q_true, int32_t r_true,
+                      rpca_relax_result *out, void *ws, size_t ws_bytes, void *stream);
 
 /* Measurement of the dominant kernel. While enabled (process-wide), every
  * streaming pass over D (the only kernel reading the m x n data) is bracketed

@@ -174,7 +174,8 @@ int validate(const rpca_params* p) {
     if (!is_fin(p->tol) || !(p->tol > 0)) return RPCA_EINVAL;
     if (!(p->flags & RPCA_FLAG_NO_TRIM) && (!is_fin(p->mu) || !(p->mu > 0))) return RPCA_EINVAL;
     if (p->max_iter < 0 || p->init_max_passes < 0) return RPCA_EINVAL;
-    if (p->flags & ~(RPCA_FLAG_NO_TRIM | RPCA_FLAG_MIXED)) return RPCA_EINVAL;
+    if (p->flags & ~(RPCA_FLAG_NO_TRIM | RPCA_FLAG_MIXED | RPCA_FLAG_TRAINING)) return RPCA_EINVAL;
+    if ((p->flags & RPCA_FLAG_TRAINING) && p->r > RX_KMAX) return RPCA_EINVAL;
     if ((p->flags & RPCA_FLAG_MIXED) && p->dtype != RPCA_F32) return RPCA_EINVAL;
     if (!(p->mixed_err == p->mixed_err) || isinf(p->mixed_err)) return RPCA_EINVAL;
     if (p->init_block != 0) {
@@ -194,6 +195,9 @@ struct Layout {
     size_t off_ctrl, off_small, off_hist, off_P1, off_P2, off_resid, off_gpart;
     size_t off_Y1, off_Y2, off_W1, off_W2, off_Ap, off_Bp, off_Unew, off_Vnew;
     size_t off_Uf, off_Vf, off_AL, off_BL;
+    // relaxed iteration (RPCA_FLAG_TRAINING)
+    int rx_nct, rx_nrt, rx_TM;
+    size_t off_R1, off_R2, off_Rres, off_RY1, off_RY2, off_gpR, off_gram, off_gram2, off_coef, off_rres;
     size_t total;
 };
 
@@ -242,6 +246,28 @@ Layout make_layout(const rpca_params* p) {
     const size_t tm = L.elt * (size_t)m * L.KW, tn = L.elt * (size_t)n * L.KW;
     L.off_Uf = take(tm); L.off_Vf = take(tn);
     L.off_AL = take(tm); L.off_BL = take(tn);
+    L.rx_nct = L.rx_nrt = L.rx_TM = 0;
+    L.off_R1 = L.off_R2 = L.off_Rres = L.off_RY1 = L.off_RY2 = L.off_gpR = L.off_gram = L.off_gram2 = 0;
+    L.off_coef = L.off_rres = 0;
+    if (p->flags & RPCA_FLAG_TRAINING) {
+        const int K2 = 2 * p->r;
+        L.rx_nct = (n + RX_THREADS - 1) / RX_THREADS;
+        int nrt = (m + 63) / 64;
+        if (nrt > RX_MAX_RT) nrt = RX_MAX_RT;
+        L.rx_TM = (m + nrt - 1) / nrt;
+        L.rx_nrt = (m + L.rx_TM - 1) / L.rx_TM;
+        const int gp = (m + 255) / 256 + (n + 255) / 256;
+        L.off_R1 = take(sizeof(double) * (size_t)L.rx_nct * m * K2);
+        L.off_R2 = take(sizeof(double) * (size_t)L.rx_nrt * n * K2);
+        L.off_Rres = take(sizeof(double) * (size_t)L.rx_nct * L.rx_nrt);
+        L.off_RY1 = take(sizeof(double) * (size_t)m * K2);
+        L.off_RY2 = take(sizeof(double) * (size_t)n * K2);
+        L.off_gpR = take(sizeof(double) * (size_t)gp * RX_WMAX * RX_WMAX);
+        L.off_gram = take(sizeof(double) * 2 * RX_WMAX * RX_WMAX);
+        L.off_gram2 = take(sizeof(double) * 2 * RX_WMAX * RX_WMAX);
+        L.off_coef = take(sizeof(double) * 6 * KMAX * KMAX);
+        L.off_rres = take(sizeof(RelaxResult));
+    }
     L.total = off;
     return L;
 }
@@ -685,6 +711,82 @@ int rpca_step(const void* D, const rpca_params* p, rpca_state* st, void* ws, siz
     Ctrl t;
     RPCA_TRY(read_ctrl(c, &t));
     fill_state(st, t);
+    return RPCA_OK;
+}
+
+int rpca_relaxed_step(const void* D, const rpca_params* p, rpca_state* st, double zeta, double tau,
+                      const double* P_true, const double* Q_true, int32_t r_true, rpca_relax_result* out, void* ws,
+                      size_t ws_bytes, void* stream) {
+    if (!D || !P_true || !Q_true || !out) return RPCA_EINVAL;
+    RPCA_TRY(check_state(st));
+    if (!p || !(p->flags & RPCA_FLAG_TRAINING)) return RPCA_EINVAL;
+    if (r_true < 1 || r_true > RX_TRUE_MAX) return RPCA_EINVAL;
+    if (!is_fin(zeta) || !(zeta > 0) || !is_fin(tau) || !(tau > 0)) return RPCA_EINVAL;
+    Ctx c;
+    RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
+    double nd2 = st->normD > 0 ? st->normD * st->normD : 0.0;
+    if (!(nd2 > 0)) RPCA_TRY(compute_normD2(c, D, &nd2));
+    RPCA_TRY(setup(c, base_ctrl(c, STAGE_MAIN, zeta, st->k, nd2, 0)));
+    const int K = p->r;
+    // Trim(L_k): bases U_f, V_f (with R_U, R_V) and the rebuild factors of L_k
+    RPCA_TRY(enqueue_enter(c, st->U, st->V, K, st->sigma, nullptr, nullptr, nullptr));
+    const Layout& L = c.L;
+    RelaxArgs a;
+    memset(&a, 0, sizeof(a));
+    a.D = D;
+    a.ldd = p->ldd;
+    a.m = (int)p->m;
+    a.n = (int)p->n;
+    a.K = K;
+    a.rt_true = r_true;
+    a.AL = c.ws + L.off_AL;
+    a.BL = c.ws + L.off_BL;
+    a.Uf = c.ws + L.off_Uf;
+    a.Vf = c.ws + L.off_Vf;
+    a.zeta = zeta;
+    a.tau = tau;
+    a.normD2 = nd2;
+    a.TM = L.rx_TM;
+    a.n_ct = L.rx_nct;
+    a.n_rt = L.rx_nrt;
+    a.n_tiles = L.rx_nct * L.rx_nrt;
+    a.gU = (a.m + 255) / 256;
+    a.gV = (a.n + 255) / 256;
+    a.R1 = c.at<double>(L.off_R1);
+    a.R2 = c.at<double>(L.off_R2);
+    a.Rres = c.at<double>(L.off_Rres);
+    a.RY1 = c.at<double>(L.off_RY1);
+    a.RY2 = c.at<double>(L.off_RY2);
+    a.gpartR = c.at<double>(L.off_gpR);
+    a.gram = c.at<double>(L.off_gram);
+    a.gram2 = c.at<double>(L.off_gram2);
+    a.P = P_true;
+    a.Q = Q_true;
+    a.RUinv = c.small()->RUinv;
+    a.RVinv = c.small()->RVinv;
+    a.coef = c.at<double>(L.off_coef);
+    a.sigma_out = st->sigma;
+    a.Uout = st->U;
+    a.Vout = st->V;
+    a.result = c.at<RelaxResult>(L.off_rres);
+    a.ctrl = c.ctrl();
+    HIP_TRY(launch_relax(a, c.dtype, c.s));
+    RelaxResult r;
+    HIP_TRY(hipMemcpyAsync(&r, a.result, sizeof(r), hipMemcpyDeviceToHost, c.s));
+    HIP_TRY(hipStreamSynchronize(c.s));
+    out->loss = r.loss;
+    out->dloss_dzeta = r.dloss_dzeta;
+    out->err = r.err;
+    out->sigma1 = r.sigma1;
+    out->sigma_r1 = r.sigma_r1;
+    out->svd_sweeps = r.sweeps;
+    out->reserved = 0;
+    st->zeta = zeta;
+    st->err = r.err;
+    st->k += 1;
+    st->sigma1_pt = r.sigma1;
+    st->sigma_r1_pt = r.sigma_r1;
+    st->normD = sqrt(nd2);
     return RPCA_OK;
 }
 

@@ -17,6 +17,12 @@ constexpr int PANEL_THREADS = 256;
 constexpr int GATHER_SPLIT = 8;   // adjacent lanes sharing one row in the gather kernel (<= 16)
 constexpr int GATHER_THREADS = 1024;
 constexpr int GPART_STRIDE = 2 * KMAX * KMAX;   // doubles per workgroup partial slot
+// relaxed iteration (threshold training)
+constexpr int RX_KMAX = 10;        // largest rank of the relaxed iteration (3r <= 30 for the wave SVD)
+constexpr int RX_TRUE_MAX = 16;    // largest rank of the loss's target factors
+constexpr int RX_THREADS = 256;    // columns per tile of its pass over D (one per thread)
+constexpr int RX_MAX_RT = 16;      // row tiles of that pass
+constexpr int RX_WMAX = 3 * RX_KMAX + RX_TRUE_MAX;   // widest Gram, [F Y dY P]
 
 // Stages of the device-side state machine (Ctrl::stage).
 enum Stage : int {
@@ -35,7 +41,7 @@ enum Body : int {
 
 // Counter slots for the last-workgroup-finishes pattern.
 enum CounterSlot : int {
-    CNT_GATHER = 0, CNT_COMPLEMENT = 1, CNT_UPDATE = 2, CNT_BASIS = 3, CNT_START = 4,
+    CNT_GATHER = 0, CNT_COMPLEMENT = 1, CNT_UPDATE = 2, CNT_BASIS = 3, CNT_START = 4, CNT_RELAX = 5,
     CNT_COUNT = 8,
 };
 

@@ -78,6 +78,33 @@ struct PanelArgs {
     int32_t gated;            // basis kernel: skip when the body is not active
 };
 
+// Results of one relaxed iteration (device, written by its tail kernel).
+struct RelaxResult {
+    double loss, dloss_dzeta;   // ||L_{k+1} - P Q^T||^2 / ||P Q^T||^2 and its zeta-derivative
+    double err;                 // ||x - s(x)||_F / ||D||_F at L_k (relaxed err_k)
+    double sigma1, sigma_r1;    // sigma_1 and sigma_{r+1} of P_T(Z)
+    int32_t sweeps, pad;
+};
+
+// Arguments of the relaxed iteration's kernels (see relax.hip).
+struct RelaxArgs {
+    const void* D; int64_t ldd;
+    int32_t m, n, K, rt_true;
+    const void* AL; const void* BL; const void* Uf; const void* Vf;
+    double zeta, tau, normD2;
+    int32_t TM, n_ct, n_rt, n_tiles, gU, gV;
+    double* R1; double* R2; double* Rres;   // per-tile partials [n_ct][m][2K], [n_rt][n][2K]
+    double* RY1; double* RY2;               // [Y1 dY1] (m x 2K), [Y2 dY2] (n x 2K)
+    double* gpartR;                         // Gram partials
+    double* gram;  double* gram2;           // [F Y dY P] and [W dW P] Grams, U side then V side
+    const double* P; const double* Q;       // target factors, m x rt_true and n x rt_true
+    const double* RUinv; const double* RVinv;
+    double* coef;                           // 6 K x K coefficient blocks of the new factors
+    double* sigma_out; double* Uout; double* Vout;
+    RelaxResult* result;
+    Ctrl* ctrl;
+};
+
 enum UpdateMode : int { UPDATE_FROM_M = 0, UPDATE_ENTER = 1, UPDATE_ENTER_EXACT = 2 };
 enum GatherMode : int { GATHER_ONLY = 0, GATHER_WITH_SVD = 1 };
 
@@ -94,6 +121,7 @@ hipError_t launch_update(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_basis(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_start(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, hipStream_t s);
+hipError_t launch_relax(const RelaxArgs& a, int dtype, hipStream_t s);
 hipError_t launch_convert(const double* src, void* dst, int64_t count, const double* scale, int K,
                           int dtype, hipStream_t s);
 

@@ -1,0 +1,315 @@
+// Single-wave and whole-workgroup helpers of the small FP64 algebra: LDS
+// matrix moves and products, fixed-order sums of per-workgroup partials, a
+// two-at-once Cholesky factorisation with inverses, and a one-sided Jacobi
+// SVD run by one wave. Shared by the panel kernels of the loop and of the
+// relaxed iteration.
+#pragma once
+
+#include "common.hpp"
+
+namespace rpca {
+namespace {
+
+constexpr double JACOBI_EPS = 1e-15;
+// Pairs with |a_p . a_q| <= JACOBI_ABS ||M||_F^2 are left alone: such a coupling
+// moves the leading singular vectors by about that relative amount, and the
+// trailing (negligible) columns would otherwise keep rotating on rounding noise.
+constexpr double JACOBI_ABS = 1e-17;
+constexpr int JACOBI_MAX_SWEEPS = 40;
+constexpr double CHOL_DEAD_REL = 1e-26;
+
+// ---- single-wave helpers (the last workgroup's tail) ---------------------------
+
+__device__ inline int lane_id() { return threadIdx.x & (WAVE - 1); }
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int K>
+__device__ inline void w_load(const double* __restrict__ g, double* s) {
+    for (int e = lane_id(); e < K * K; e += WAVE) s[e] = g[(e / K) * KMAX + (e % K)];
+    wave_sync();
+}
+template <int K>
+__device__ inline void w_store(const double* s, double* __restrict__ g) {
+    for (int e = lane_id(); e < K * K; e += WAVE) g[(e / K) * KMAX + (e % K)] = s[e];
+    wave_sync();
+}
+// C = op(A) B (K x K, ld K, LDS); op = transpose when TA
+template <int K, bool TA>
+__device__ inline void w_mm(const double* A, const double* B, double* C) {
+    for (int e = lane_id(); e < K * K; e += WAVE) {
+        const int i = e / K, j = e % K;
+        double acc = 0.0;
+        for (int l = 0; l < K; ++l) acc = fma(TA ? A[l * K + i] : A[i * K + l], B[l * K + j], acc);
+        C[e] = acc;
+    }
+    wave_sync();
+}
+
+// Sums of the per-workgroup partials of a kernel whose first gU workgroups
+// cover the U side (rows of m) and the next gV the V side (rows of n). Job j
+// sums entry e < E of the partial at offset (j / 2) * KMAX^2 of every
+// workgroup of side j % 2, into out[j * E + e].
+// The whole workgroup (NT threads) takes part. Thread t takes pair
+// q = t % PAIRS (job q / E, entry q % E) and split s = t / PAIRS and sums the
+// partials b = s, s + S, ... in order; the S split sums of a pair are then
+// added in order of s. Up to 16 loads per thread are in flight at once, so a
+// round over up to 16 S partials costs one memory latency. part: NT doubles
+// of LDS.
+template <int E, int J, int NT>
+__device__ void block_sum_partials(const double* __restrict__ gpart, int gU, int gV, double* out, double* part) {
+    constexpr int PAIRS = J * E;
+    constexpr int PR = PAIRS >= NT ? NT : PAIRS;   // pairs per round
+    constexpr int S = NT / PR;                     // splits per pair
+    constexpr int L = 16;                          // loads in flight per thread
+    const int t = threadIdx.x;
+    for (int q0 = 0; q0 < PAIRS; q0 += PR) {
+        const int sp = t / PR, q = q0 + t % PR;
+        double acc = 0.0;
+        if (sp < S && q < PAIRS) {
+            const int j = q / E, e = q - (q / E) * E;
+            const int first = (j & 1) ? gU : 0, count = (j & 1) ? gV : gU;
+            const double* g = gpart + (size_t)first * GPART_STRIDE + (j >> 1) * (KMAX * KMAX) + e;
+            for (int b0 = sp; b0 < count; b0 += L * S) {
+                double v[L];
+#pragma unroll
+                for (int u = 0; u < L; ++u) {
+                    const int b = b0 + u * S;
+                    v[u] = b < count ? g[(size_t)b * GPART_STRIDE] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < L; ++u) acc += v[u];
+            }
+        }
+        if (t < S * PR) part[t] = acc;
+        __syncthreads();
+        if (t < PR && q0 + t < PAIRS) {
+            double v = 0.0;
+            for (int u = 0; u < S; ++u) v += part[u * PR + t];
+            out[q0 + t] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// Sum of the per-tile residuals (and, if want_max, the max of the per-tile
+// max |D_ij| stored after them) by the whole workgroup, in a fixed order.
+// out[0] = sum, out[1] = max. part: at least 2 * NT / WAVE doubles of LDS.
+template <int NT>
+__device__ void block_resid(const double* __restrict__ resid, int n_tiles, bool want_max, double* part,
+                            double* out) {
+    const int t = threadIdx.x;
+    double sm = 0.0, mx = 0.0;
+    for (int b = t; b < n_tiles; b += NT) {
+        sm += resid[b];
+        if (want_max) mx = fmax(mx, resid[n_tiles + b]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sm += __shfl_xor(sm, off, WAVE);
+        mx = fmax(mx, __shfl_xor(mx, off, WAVE));
+    }
+    constexpr int NW = NT / WAVE;
+    if ((t & (WAVE - 1)) == 0) {
+        part[t / WAVE] = sm;
+        part[NW + t / WAVE] = mx;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double a = 0.0, m = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            a += part[w];
+            m = fmax(m, part[NW + w]);
+        }
+        out[0] = a;
+        out[1] = m;
+    }
+    __syncthreads();
+}
+
+__device__ inline double readlane64(double x, int l) {
+    const int64_t u = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Two Cholesky factorisations at once, G0 = R0^T R0 in lanes 0..31 and
+// G1 = R1^T R1 in lanes 32..63, with the inverses R^{-1} (all K x K, ld K,
+// LDS; R upper triangular). Lane c of a half owns column c in registers; the
+// factorisation is right-looking: at step j the pivot and row j of R are
+// formed in registers and broadcast with readlane, and the trailing columns
+// are updated. A pivot that vanishes (d <= CHOL_DEAD_REL * G_jj, or G_jj ~ 0)
+// marks a numerically dependent column: its row of R and column of R^{-1}
+// are 0. R^{-1} by back substitution from R in LDS, column c in lane c.
+template <int K>
+__device__ void w_chol_inv2(const double* G0, double* R0, double* Ri0, const double* G1, double* R1,
+                            double* Ri1) {
+    static_assert(K <= 32, "one column per lane of a half wave");
+    const int lane = lane_id();
+    const int h = lane >> 5, c = lane & 31;
+    const double* G = h ? G1 : G0;
+    double g[K], r[K], inv[K], x[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) g[i] = c < K ? G[i * K + c] : 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const double d = h ? readlane64(g[j], 32 + j) : readlane64(g[j], j);
+        const double gjj = G[j * K + j];
+        const bool live = gjj > 1e-300 && d > CHOL_DEAD_REL * gjj;
+        const double rjj = live ? sqrt(d) : 0.0;
+        const double ivj = live ? 1.0 / rjj : 0.0;
+        inv[j] = ivj;
+        r[j] = (c == j) ? rjj : (c > j ? g[j] * ivj : 0.0);   // R[j][c]
+#pragma unroll
+        for (int i = j + 1; i < K; ++i) {
+            const double rji = h ? readlane64(r[j], 32 + i) : readlane64(r[j], i);
+            g[i] = fma(-rji, r[j], g[i]);
+        }
+    }
+    double* R = h ? R1 : R0;
+    double* Ri = h ? Ri1 : Ri0;
+    if (c < K) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) R[i * K + c] = r[i];
+    }
+    wave_sync();
+    // back substitution with R read from LDS (same address in all lanes of a half)
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+        double v = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = i + 1; k < K; ++k) v = fma(-R[i * K + k], x[k], v);
+        x[i] = v * inv[i];
+    }
+    if (c < K) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) Ri[i * K + c] = x[i];
+    }
+    wave_sync();
+}
+
+template <int CTRL> __device__ inline double dpp64(double x) {
+    const int64_t u = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+// Sum over aligned groups of LP lanes (LP = 1, 2, 4, 8, 16), result in every lane.
+template <int LP> __device__ inline double group_sum(double x) {
+    if constexpr (LP >= 2) x += dpp64<0xB1>(x);    // quad_perm[1,0,3,2]: lane ^ 1
+    if constexpr (LP >= 4) x += dpp64<0x4E>(x);    // quad_perm[2,3,0,1]: lane ^ 2
+    if constexpr (LP >= 8) x += dpp64<0x141>(x);   // row_half_mirror:    lane ^ 7
+    if constexpr (LP >= 16) x += dpp64<0x128>(x);  // row_ror:8:          lane ^ 8
+    return x;
+}
+
+constexpr int pow2_floor(int x) { int p = 1; while (p * 2 <= x) p *= 2; return p; }
+
+// One-sided (Hestenes) Jacobi SVD of the N x N matrix A (LDS, column-major),
+// run by a single wave: the N/2 disjoint column pairs of a round-robin round
+// are processed at once, LP lanes per pair, with DPP reductions for the three
+// inner products. A pair is rotated when |a_p . a_q| > JACOBI_EPS ||a_p|| ||a_q||
+// and above the absolute floor JACOBI_ABS ||A||_F^2 (pairs of negligible
+// columns would otherwise rotate on rounding noise). Sweeps stop when no pair
+// was rotated. On return sig[] is descending and Uo/Vo hold the left/right
+// singular vectors as columns (column-major). Returns the sweep count.
+template <int N>
+__device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, double* Vo) {
+    static_assert(N % 2 == 0 && N <= 2 * KMAX, "even N up to 2*KMAX");
+    constexpr int NP = N / 2;
+    constexpr int LP0 = pow2_floor(WAVE / NP);
+    constexpr int LP = LP0 > 16 ? 16 : LP0;
+    constexpr int E = (N + LP - 1) / LP;
+    const int lane = lane_id();
+    double fro = 0.0;
+    for (int e = lane; e < N * N; e += WAVE) {
+        V[e] = ((e / N) == (e % N)) ? 1.0 : 0.0;
+        fro = fma(A[e], A[e], fro);
+    }
+    for (int off = 32; off > 0; off >>= 1) fro += __shfl_xor(fro, off, WAVE);
+    const double floor_abs = JACOBI_ABS * fro;
+    wave_sync();
+    const int q = lane / LP, g = lane % LP;
+    int sweep = 0;
+    for (; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
+        bool rotated = false;
+        for (int rd = 0; rd < N - 1; ++rd) {
+            if (q < NP) {
+                const int a = (q == 0) ? 0 : ((q - 1 + rd) % (N - 1)) + 1;
+                const int b = ((N - 2 - q + rd) % (N - 1)) + 1;
+                double xa[E], xb[E], va[E], vb[E];
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int u = 0; u < E; ++u) {
+                    const int e = g + LP * u;
+                    const bool ok = e < N;
+                    xa[u] = ok ? A[a * N + e] : 0.0;
+                    xb[u] = ok ? A[b * N + e] : 0.0;
+                    va[u] = ok ? V[a * N + e] : 0.0;
+                    vb[u] = ok ? V[b * N + e] : 0.0;
+                    al = fma(xa[u], xa[u], al);
+                    be = fma(xb[u], xb[u], be);
+                    ga = fma(xa[u], xb[u], ga);
+                }
+                al = group_sum<LP>(al);
+                be = group_sum<LP>(be);
+                ga = group_sum<LP>(ga);
+                if (ga * ga > (JACOBI_EPS * JACOBI_EPS) * (al * be) && fabs(ga) > floor_abs) {
+                    // tangent of the rotation angle: the root of smaller modulus of
+                    // t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga), written
+                    // without forming zeta
+                    const double dl = be - al;
+                    const double hyp = sqrt(fma(dl, dl, 4.0 * ga * ga));
+                    const double t = (dl >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(dl) + hyp);
+                    const double c = rsqrt(fma(t, t, 1.0));
+                    const double s = c * t;
+#pragma unroll
+                    for (int u = 0; u < E; ++u) {
+                        const int e = g + LP * u;
+                        if (e < N) {
+                            A[a * N + e] = c * xa[u] - s * xb[u];
+                            A[b * N + e] = s * xa[u] + c * xb[u];
+                            V[a * N + e] = c * va[u] - s * vb[u];
+                            V[b * N + e] = s * va[u] + c * vb[u];
+                        }
+                    }
+                    rotated = true;
+                }
+            }
+            wave_sync();
+        }
+        if (!__any(rotated)) break;
+    }
+    // column norms, ranks (descending, ties by index), normalised outputs
+    if (lane < N) {
+        double acc = 0.0;
+        for (int e = 0; e < N; ++e) acc = fma(A[lane * N + e], A[lane * N + e], acc);
+        sig[lane] = sqrt(acc);
+    }
+    wave_sync();
+    double sj = 0.0;
+    int rank = 0;
+    if (lane < N) {
+        sj = sig[lane];
+        for (int i = 0; i < N; ++i) {
+            const double si = sig[i];
+            rank += (si > sj) || (si == sj && i < lane);
+        }
+    }
+    wave_sync();
+    if (lane < N) {
+        sig[rank] = sj;
+        const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+        for (int e = 0; e < N; ++e) {
+            Uo[rank * N + e] = A[lane * N + e] * inv;
+            Vo[rank * N + e] = V[lane * N + e];
+        }
+    }
+    wave_sync();
+    return sweep + 1;
+}
+
+}  // namespace
+}  // namespace rpca

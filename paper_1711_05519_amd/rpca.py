@@ -27,12 +27,14 @@ RPCA_OK, RPCA_MAXITER = 0, 1
 RPCA_F64, RPCA_F32 = 0, 1
 RPCA_FLAG_NO_TRIM = 1
 RPCA_FLAG_MIXED = 2
+RPCA_FLAG_TRAINING = 4
 RPCA_PROF_KINDS = 2
 RPCA_MAX_RANK = 16
 
 EXPORTED = ("rpca_workspace_size", "rpca_init", "rpca_trim", "rpca_step", "rpca_solve",
             "rpca_materialize", "rpca_tangent_products", "rpca_strerror",
-            "rpca_last_hip_error", "rpca_version", "rpca_profile_enable", "rpca_profile_read")
+            "rpca_last_hip_error", "rpca_version", "rpca_profile_enable", "rpca_profile_read",
+            "rpca_relaxed_step")
 
 
 class RpcaError(RuntimeError):
@@ -62,6 +64,12 @@ class State(ctypes.Structure):
                 ("svd_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class RelaxResult(ctypes.Structure):
+    _fields_ = [("loss", ctypes.c_double), ("dloss_dzeta", ctypes.c_double), ("err", ctypes.c_double),
+                ("sigma1", ctypes.c_double), ("sigma_r1", ctypes.c_double),
+                ("svd_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 _LIB = None
 
 
@@ -82,6 +90,7 @@ def _lib():
             "rpca_solve": [vp, P, S, pd, pd, ctypes.c_int32, vp, sz, vp],
             "rpca_materialize": [vp, P, S, vp, ctypes.c_int64, vp, ctypes.c_int64, vp, sz, vp],
             "rpca_tangent_products": [vp, P, vp, vp, d, vp, vp, vp, vp, pd, vp, sz, vp],
+            "rpca_relaxed_step": [vp, P, S, d, d, vp, vp, ctypes.c_int32, ctypes.POINTER(RelaxResult), vp, sz, vp],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -149,6 +158,19 @@ def rpca_step(D, params, state, ws, stream=None) -> int:
                   "rpca_step")
 
 
+def rpca_relaxed_step(D, params, state, zeta, tau, P, Q, ws, stream=None) -> RelaxResult:
+    """One relaxed iteration (see include/rpca.h); P, Q: FP64 device factors."""
+    if P.dtype != torch.float64 or Q.dtype != torch.float64 or P.shape[1] != Q.shape[1]:
+        raise ValueError("P and Q must be FP64 with the same number of columns")
+    P, Q = P.contiguous(), Q.contiguous()
+    out = RelaxResult()
+    w, nb = _ws(ws)
+    _check(_lib().rpca_relaxed_step(_ptr(D), ctypes.byref(params), ctypes.byref(state), float(zeta), float(tau),
+                                    _ptr(P), _ptr(Q), int(P.shape[1]), ctypes.byref(out), w, nb, _stream(stream)),
+           "rpca_relaxed_step")
+    return out
+
+
 def rpca_solve(D, params, state, err_hist, zeta_hist, ws, stream=None) -> int:
     """err_hist / zeta_hist: ctypes double arrays (or None)."""
     w, nb = _ws(ws)
@@ -214,7 +236,8 @@ class SolveInfo:
 
 def make_params(D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: float, mu: float,
                 tol: float = 1e-5, max_iter: int = 100, trim: bool = True, init_block: int = 0,
-                init_max_passes: int = 0, seed: int = 0, mixed: bool = False, mixed_err: float = 0.0) -> Params:
+                init_max_passes: int = 0, seed: int = 0, mixed: bool = False, mixed_err: float = 0.0,
+                training: bool = False) -> Params:
     if D.dim() != 2 or D.stride(1) != 1:
         raise ValueError("D must be a 2-D row-major tensor with unit column stride")
     if D.dtype == torch.float64:
@@ -226,7 +249,8 @@ def make_params(D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: f
     return Params(m=D.shape[0], n=D.shape[1], ldd=D.stride(0), r=int(r), dtype=dt, beta=float(beta),
                   beta_init=float(beta_init), gamma=float(gamma), mu=float(mu) if trim else 0.0, tol=float(tol),
                   max_iter=int(max_iter), init_block=int(init_block), init_max_passes=int(init_max_passes),
-                  flags=(0 if trim else RPCA_FLAG_NO_TRIM) | (RPCA_FLAG_MIXED if mixed else 0), seed=int(seed),
+                  flags=((0 if trim else RPCA_FLAG_NO_TRIM) | (RPCA_FLAG_MIXED if mixed else 0)
+                         | (RPCA_FLAG_TRAINING if training else 0)), seed=int(seed),
                   mixed_err=float(mixed_err))
 
 
@@ -235,12 +259,13 @@ class Solver:
 
     def __init__(self, D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: float, mu: float,
                  tol: float = 1e-5, max_iter: int = 100, trim: bool = True, init_block: int = 0,
-                 init_max_passes: int = 0, seed: int = 0, mixed: bool = False, mixed_err: float = 0.0):
+                 init_max_passes: int = 0, seed: int = 0, mixed: bool = False, mixed_err: float = 0.0,
+                 training: bool = False):
         if not D.is_cuda:
             raise ValueError("D must be a device tensor")
         self.D = D
         self.params = make_params(D, r, beta, beta_init, gamma, mu, tol, max_iter, trim, init_block,
-                                  init_max_passes, seed, mixed, mixed_err)
+                                  init_max_passes, seed, mixed, mixed_err, training)
         dev = D.device
         m, n = D.shape
         self.U = torch.zeros((m, r), dtype=torch.float64, device=dev)
@@ -308,3 +333,38 @@ class Solver:
 
     def L_factors(self):
         return self.U, self.sigma, self.V
+
+    def relaxed_step(self, zeta: float, tau: float, P: torch.Tensor, Q: torch.Tensor) -> RelaxResult:
+        """One relaxed iteration from the current state (needs training=True)."""
+        return rpca_relaxed_step(self.D, self.params, self.state, zeta, tau, P, Q, self.ws)
+
+    def get_state(self):
+        """(U, sigma, V, zeta, k, normD) copies of the current state."""
+        return (self.U.clone(), self.sigma.clone(), self.V.clone(), self.state.zeta, self.state.k,
+                self.state.normD)
+
+    def put_state(self, saved) -> None:
+        U, s, V, zeta, k, normD = saved
+        self.U.copy_(U)
+        self.sigma.copy_(s)
+        self.V.copy_(V)
+        self.state.zeta, self.state.k, self.state.normD = float(zeta), int(k), float(normD)
+
+
+class RelaxedStep(torch.autograd.Function):
+    """loss = RelaxedStep.apply(zeta, solver, P, Q, tau): one relaxed iteration
+    of `solver` (its state advances to L_{k+1}) with the hand-written adjoint
+    in zeta. The state is data here, not a differentiable input: backward
+    returns d loss / d zeta (times the incoming gradient) and nothing else."""
+
+    @staticmethod
+    def forward(ctx, zeta, solver, P, Q, tau):
+        res = solver.relaxed_step(float(zeta), float(tau), P, Q)
+        ctx.dloss = res.dloss_dzeta
+        ctx.result = res
+        return torch.tensor(res.loss, dtype=torch.float64, device=zeta.device)
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        g = grad_loss * ctx.dloss
+        return g, None, None, None, None

@@ -57,9 +57,9 @@ def test_workspace_size_and_version(lib):
 @pytest.mark.parametrize("bad", [
     dict(m=0), dict(n=0), dict(ldd=79), dict(r=0), dict(r=17), dict(r=41), dict(dtype=7),
     dict(beta=0.0), dict(beta_init=-1.0), dict(gamma=1.0), dict(gamma=-0.1), dict(tol=0.0),
-    dict(mu=0.0), dict(max_iter=-1), dict(init_block=2), dict(init_block=17), dict(flags=4),
+    dict(mu=0.0), dict(max_iter=-1), dict(init_block=2), dict(init_block=17), dict(flags=8),
     dict(beta=float("nan")), dict(tol=float("inf")),
-    dict(flags=2, dtype=0), dict(flags=2, dtype=1, mixed_err=float("nan")),
+    dict(flags=2, dtype=0), dict(flags=2, dtype=1, mixed_err=float("nan")), dict(flags=4, r=11, m=300, n=300, ldd=300),
 ])
 def test_invalid_params_rejected(lib, bad):
     with pytest.raises(R.RpcaError) as e:
@@ -88,3 +88,28 @@ def test_null_pointers_rejected_before_launch(lib):
     d = ctypes.c_double(0)
     assert lib.rpca_init(ctypes.byref(d), ctypes.byref(p), ctypes.byref(st), ws, 16, None) == -1
     assert lib.rpca_trim(ctypes.byref(p), ctypes.byref(st), None, None, ws, 16, None) == -1
+
+
+def test_training_workspace_is_larger(lib):
+    base = R.rpca_workspace_size(_params(m=1000, n=900, ldd=900))
+    assert R.rpca_workspace_size(_params(m=1000, n=900, ldd=900, flags=R.RPCA_FLAG_TRAINING)) > base
+
+
+def test_relaxed_step_validates_before_launch(lib):
+    p = _params(flags=R.RPCA_FLAG_TRAINING)
+    st = R.State()
+    out = R.RelaxResult()
+    d = ctypes.c_double(0)
+    ws = ctypes.create_string_buffer(16)
+    # state without buffers, then missing factors: rejected before any device work
+    assert lib.rpca_relaxed_step(ctypes.byref(d), ctypes.byref(p), ctypes.byref(st), 1.0, 0.1,
+                                 ctypes.byref(d), ctypes.byref(d), 1, ctypes.byref(out), ws, 16, None) == -1
+    st.U = st.V = st.sigma = ctypes.addressof(d)
+    assert lib.rpca_relaxed_step(ctypes.byref(d), ctypes.byref(p), ctypes.byref(st), 1.0, 0.1,
+                                 None, None, 1, ctypes.byref(out), ws, 16, None) == -1
+    for zeta, tau, rt in [(0.0, 0.1, 1), (1.0, 0.0, 1), (float("nan"), 0.1, 1), (1.0, 0.1, 0), (1.0, 0.1, 17)]:
+        assert lib.rpca_relaxed_step(ctypes.byref(d), ctypes.byref(p), ctypes.byref(st), zeta, tau,
+                                     ctypes.byref(d), ctypes.byref(d), rt, ctypes.byref(out), ws, 16, None) == -1
+    p2 = _params()   # no training workspace
+    assert lib.rpca_relaxed_step(ctypes.byref(d), ctypes.byref(p2), ctypes.byref(st), 1.0, 0.1,
+                                 ctypes.byref(d), ctypes.byref(d), 1, ctypes.byref(out), ws, 16, None) == -1
