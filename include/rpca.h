@@ -66,6 +66,16 @@ extern "C" {
 #define RPCA_FLAG_MIXED 2u
 /* Workspace for rpca_relaxed_step (threshold training; r <= 10). */
 #define RPCA_FLAG_TRAINING 4u
+/* Learned threshold schedule (not part of the paper): in the loop, zeta_{k+1}
+ * = beta (sigma_{r+1} + gamma^{k+1} sigma_1) * exp(clip(o, -5, 5)), a learned
+ * correction of Algorithm 1's threshold, with o the output of the threshold
+ * network (params->zeta_mlp, RPCA_MLP_PARAMS device floats) at the features
+ *   phi = ((k + 1) / 15, log(sigma_{r+1} / sigma_1), log err_k, log(sigma_1 / ||D||_F)),
+ * sigma_1, sigma_{r+1} those of P_T(D - S_k). Fallback to the paper's
+ * schedule of Algorithm 1 for the rest of the solve as soon as err_k >= err_{k-1}
+ * or the network's threshold is not a positive finite number. */
+#define RPCA_FLAG_LEARNED 8u
+#define RPCA_MLP_PARAMS 1249
 
 /* Largest supported rank r and init block p. */
 #define RPCA_MAX_RANK 16
@@ -89,6 +99,7 @@ typedef struct rpca_params {
     uint64_t seed;         /* seeds the start block of the initial truncated SVD             */
     double   mixed_err;    /* with RPCA_FLAG_MIXED: BF16-product bodies while err_k >= this;
                               <= 0 selects the default 1e-3                                  */
+    const float *zeta_mlp; /* with RPCA_FLAG_LEARNED: device parameters of the network      */
 } rpca_params;
 
 /* Iterate (L_k, S_k): L_k = U diag(sigma) V^T, S_k = T_zeta(D - L_k). The three
@@ -188,6 +199,20 @@ typedef struct {
 int rpca_relaxed_step(const void *D, const rpca_params *p, rpca_state *st, double zeta, double tau,
                       const double *P_true, const double *Q_true, int32_t r_true,
                       rpca_relax_result *out, void *ws, size_t ws_bytes, void *stream);
+
+/* Training kernels of the threshold network (device FP32 arrays, ordered
+ * on stream; parameter layout W1 (32 x 4, row-major), b1 (32), W2 (32 x 32),
+ * b2 (32), w3 (32), b3 (1), RPCA_MLP_PARAMS values):
+ *   rpca_mlp_forward:  o[b] = w3 . relu(W2 relu(W1 phi_b + b1) + b2) + b3,
+ *                      phi: batch x 4 row-major;
+ *   rpca_mlp_backward: grad_theta = sum over b (in order) of grad_o[b] d o_b / d theta
+ *                      (overwritten, not accumulated);
+ *   rpca_mlp_adam:     one Adam update (Kingma and Ba) at step t >= 1 with moments m, v. */
+int rpca_mlp_forward(const float *theta, const float *phi, int32_t batch, float *o, void *stream);
+int rpca_mlp_backward(const float *theta, const float *phi, const float *grad_o, int32_t batch,
+                      float *grad_theta, void *stream);
+int rpca_mlp_adam(float *theta, float *m, float *v, const float *grad, int32_t t, float lr,
+                  float beta1, float beta2, float eps, void *stream);
 
 /* Measurement of the dominant kernel. While enabled (process-wide), every
  * streaming pass over D (the only kernel reading the m x n data) is bracketed

@@ -5,9 +5,9 @@ zeta_{k+1} = beta (sigma_{r+1} + gamma^{k+1} sigma_1) (Algorithm 1, Section 2.1)
 This module is the plain reference for two additions built on top of it:
 
 * a small multilayer perceptron that maps features of the current iterate to a
-  threshold zeta_k (4 -> 32 -> 32 -> 1, ReLU hidden layers, softplus output
-  scaled by beta * sigma_1), its gradient and one Adam update (Kingma and Ba,
-  "Adam: a method for stochastic optimization", Algorithm 1);
+  correction of the threshold, zeta_k = zeta_paper * exp(clip(o, -5, 5))
+  (4 -> 32 -> 32 -> 1, ReLU hidden layers), its gradient and one Adam update
+  (Kingma and Ba, "Adam: a method for stochastic optimization", Algorithm 1);
 * one AccAltProj iteration with the hard threshold T_zeta replaced by the
   relaxation s(x) = x * logistic((|x| - zeta) / tau), which tends to T_zeta as
   tau -> 0, together with the derivative of a loss of the next iterate with
@@ -54,10 +54,6 @@ def features(k: int, K: int, sigma1: float, sigma_r1: float, err: float, normD: 
                      np.log(max(sigma1, f) / max(normD, f))], dtype=np.float64)
 
 
-def softplus(o: float) -> float:
-    return float(np.logaddexp(0.0, o))
-
-
 def mlp_forward(theta: np.ndarray, phi: np.ndarray):
     """Returns (o, cache): o = w3 . relu(W2 relu(W1 phi + b1) + b2) + b3."""
     W1, b1, W2, b2, w3, b3 = unpack(theta)
@@ -69,9 +65,12 @@ def mlp_forward(theta: np.ndarray, phi: np.ndarray):
     return o, (phi, a1, h1, a2, h2)
 
 
-def zeta_of(o: float, beta: float, sigma1: float) -> float:
-    """zeta = beta * sigma_1 * softplus(o)."""
-    return beta * sigma1 * softplus(o)
+O_CLIP = 5.0
+
+
+def zeta_of(o: float, zeta_paper: float) -> float:
+    """zeta = zeta_paper * exp(clip(o, -5, 5)); zeta_paper the schedule of Algorithm 1."""
+    return zeta_paper * float(np.exp(np.clip(o, -O_CLIP, O_CLIP)))
 
 
 def mlp_backward(theta: np.ndarray, cache, grad_o: float) -> np.ndarray:
@@ -101,13 +100,12 @@ def adam_step(theta, m, v, g, t: int, lr: float, b1: float = 0.9, b2: float = 0.
 
 
 def init_theta(seed: int) -> np.ndarray:
-    """He-style normal weights, zero biases, and b3 = log(e - 1) so that the
-    untrained output is softplus(b3) = 1, i.e. zeta = beta * sigma_1."""
+    """He-style normal weights, zero biases and a zero output layer: the
+    untrained output is o = 0, i.e. the paper's schedule."""
     rng = np.random.default_rng(seed)
     W1 = rng.standard_normal((N_H, N_IN)) * np.sqrt(2.0 / N_IN)
     W2 = rng.standard_normal((N_H, N_H)) * np.sqrt(2.0 / N_H)
-    w3 = rng.standard_normal(N_H) * np.sqrt(1.0 / N_H) * 0.1
-    return np.concatenate([W1.ravel(), np.zeros(N_H), W2.ravel(), np.zeros(N_H), w3, [np.log(np.e - 1.0)]])
+    return np.concatenate([W1.ravel(), np.zeros(N_H), W2.ravel(), np.zeros(N_H), np.zeros(N_H), [0.0]])
 
 
 # ------------------------------------------------ relaxed iteration ---------

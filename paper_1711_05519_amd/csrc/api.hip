@@ -174,7 +174,8 @@ int validate(const rpca_params* p) {
     if (!is_fin(p->tol) || !(p->tol > 0)) return RPCA_EINVAL;
     if (!(p->flags & RPCA_FLAG_NO_TRIM) && (!is_fin(p->mu) || !(p->mu > 0))) return RPCA_EINVAL;
     if (p->max_iter < 0 || p->init_max_passes < 0) return RPCA_EINVAL;
-    if (p->flags & ~(RPCA_FLAG_NO_TRIM | RPCA_FLAG_MIXED | RPCA_FLAG_TRAINING)) return RPCA_EINVAL;
+    if (p->flags & ~(RPCA_FLAG_NO_TRIM | RPCA_FLAG_MIXED | RPCA_FLAG_TRAINING | RPCA_FLAG_LEARNED)) return RPCA_EINVAL;
+    if ((p->flags & RPCA_FLAG_LEARNED) && !p->zeta_mlp) return RPCA_EINVAL;
     if ((p->flags & RPCA_FLAG_TRAINING) && p->r > RX_KMAX) return RPCA_EINVAL;
     if ((p->flags & RPCA_FLAG_MIXED) && p->dtype != RPCA_F32) return RPCA_EINVAL;
     if (!(p->mixed_err == p->mixed_err) || isinf(p->mixed_err)) return RPCA_EINVAL;
@@ -332,6 +333,8 @@ Ctrl base_ctrl(const Ctx& c, int stage, double zeta, int k, double normD2, int w
     // rounding level of the streamed products relative to sigma_1
     t.sigma_dead = p->dtype == RPCA_F64 ? 1e-12 : 1e-5;
     t.single = p->dtype == RPCA_F32 ? 1 : 0;
+    t.learned_on = ((p->flags & RPCA_FLAG_LEARNED) && p->zeta_mlp) ? 1 : 0;
+    t.err_prev = 1e300;
     return t;
 }
 
@@ -404,6 +407,7 @@ PanelArgs panel_args(const Ctx& c, const Geo& g = Geo{0, 1}) {
     a.BL = c.ws + c.L.off_BL;
     a.host_status = c.dev->status_dev;
     a.body = BODY_ANY;
+    a.mlp = (c.p->flags & RPCA_FLAG_LEARNED) ? c.p->zeta_mlp : nullptr;
     return a;
 }
 
@@ -787,6 +791,34 @@ int rpca_relaxed_step(const void* D, const rpca_params* p, rpca_state* st, doubl
     st->sigma1_pt = r.sigma1;
     st->sigma_r1_pt = r.sigma_r1;
     st->normD = sqrt(nd2);
+    return RPCA_OK;
+}
+
+int rpca_mlp_forward(const float* theta, const float* phi, int32_t batch, float* o, void* stream) {
+    if (!theta || !phi || !o || batch < 0) return RPCA_EINVAL;
+    DeviceInfo* dev = nullptr;
+    RPCA_TRY(device_info(&dev));
+    HIP_TRY(launch_mlp_forward(theta, phi, o, batch, static_cast<hipStream_t>(stream)));
+    return RPCA_OK;
+}
+
+int rpca_mlp_backward(const float* theta, const float* phi, const float* grad_o, int32_t batch, float* grad_theta,
+                      void* stream) {
+    if (!theta || !phi || !grad_o || !grad_theta || batch < 0) return RPCA_EINVAL;
+    DeviceInfo* dev = nullptr;
+    RPCA_TRY(device_info(&dev));
+    HIP_TRY(launch_mlp_backward(theta, phi, grad_o, batch, grad_theta, static_cast<hipStream_t>(stream)));
+    return RPCA_OK;
+}
+
+int rpca_mlp_adam(float* theta, float* m, float* v, const float* grad, int32_t t, float lr, float beta1, float beta2,
+                  float eps, void* stream) {
+    if (!theta || !m || !v || !grad || t < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||
+        !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return RPCA_EINVAL;
+    DeviceInfo* dev = nullptr;
+    RPCA_TRY(device_info(&dev));
+    HIP_TRY(launch_mlp_adam(theta, m, v, grad, t, lr, beta1, beta2, eps, static_cast<hipStream_t>(stream)));
     return RPCA_OK;
 }
 

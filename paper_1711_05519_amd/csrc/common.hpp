@@ -23,6 +23,10 @@ constexpr int RX_TRUE_MAX = 16;    // largest rank of the loss's target factors
 constexpr int RX_THREADS = 256;    // columns per tile of its pass over D (one per thread)
 constexpr int RX_MAX_RT = 16;      // row tiles of that pass
 constexpr int RX_WMAX = 3 * RX_KMAX + RX_TRUE_MAX;   // widest Gram, [F Y dY P]
+// threshold network: phi (4) -> 32 -> 32 -> 1
+constexpr int MLP_IN = 4, MLP_H = 32;
+constexpr int MLP_PARAMS = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;   // 1249
+constexpr double MLP_K_FEAT = 15.0;   // iteration count that normalises the first feature
 
 // Stages of the device-side state machine (Ctrl::stage).
 enum Stage : int {
@@ -87,6 +91,9 @@ struct Ctrl {
     double sigma_dead;   // relative size below which a singular triplet of M is dropped
     double max_abs_D;    // max |D_ij| (from the init passes, where L = 0)
     double err_ring[8];  // err_k of loop body k in slot k & 7 (published to the host)
+    double err_prev;     // err_{k-1} (fallback test of the learned schedule)
+    int32_t learned_on;  // 1 while zeta_{k+1} comes from the threshold network
+    int32_t pad2_;
     int32_t single;      // 1: D and the streamed factors are FP32
     int32_t pad_;
 };

@@ -73,6 +73,7 @@ struct PanelArgs {
     double* err_hist; double* zeta_hist; int32_t hist_cap;
     HostStatus* host_status;
     uint64_t seed;
+    const float* mlp;         // threshold network parameters (learned schedule) or null
     int32_t mode;             // kernel-specific
     int32_t body;             // Body of the gather kernel
     int32_t gated;            // basis kernel: skip when the body is not active
@@ -122,6 +123,10 @@ hipError_t launch_basis(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_start(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, hipStream_t s);
 hipError_t launch_relax(const RelaxArgs& a, int dtype, hipStream_t s);
+hipError_t launch_mlp_forward(const float* th, const float* phi, float* o, int B, hipStream_t s);
+hipError_t launch_mlp_backward(const float* th, const float* phi, const float* g, int B, float* grad, hipStream_t s);
+hipError_t launch_mlp_adam(float* th, float* m, float* v, const float* g, int t, float lr, float b1, float b2,
+                           float eps, hipStream_t s);
 hipError_t launch_convert(const double* src, void* dst, int64_t count, const double* scale, int K,
                           int dtype, hipStream_t s);
 

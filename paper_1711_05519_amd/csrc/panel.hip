@@ -92,6 +92,34 @@ __device__ inline void publish_status(const PanelArgs& a, const Ctrl* c) {
     }
 }
 
+__device__ inline bool is_finite_pos(double x) { return x > 0.0 && x < 1e300; }
+constexpr double MLP_O_CLIP = 5.0;   // the correction exp(o) stays within e^-5 .. e^5
+
+// Output o of the threshold network (parameters th, FP32, layout of the
+// training kernels) at features phi, evaluated in FP64 by one wave: lane j < 32
+// owns hidden unit j. The result is valid in every lane.
+__device__ inline double w_mlp(const float* __restrict__ th, const double (&phi)[MLP_IN]) {
+    constexpr int OB1 = MLP_H * MLP_IN, OW2 = OB1 + MLP_H, OB2 = OW2 + MLP_H * MLP_H, OW3 = OB2 + MLP_H,
+                  OB3 = OW3 + MLP_H;
+    __shared__ double h1s[MLP_H];
+    const int lane = lane_id();
+    if (lane < MLP_H) {
+        double v = th[OB1 + lane];
+        for (int i = 0; i < MLP_IN; ++i) v = fma((double)th[lane * MLP_IN + i], phi[i], v);
+        h1s[lane] = fmax(v, 0.0);
+    }
+    wave_sync();
+    double c = 0.0;
+    if (lane < MLP_H) {
+        double v = th[OB2 + lane];
+        for (int i = 0; i < MLP_H; ++i) v = fma((double)th[OW2 + lane * MLP_H + i], h1s[i], v);
+        c = (double)th[OW3 + lane] * fmax(v, 0.0);
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, WAVE);
+    wave_sync();
+    return c + (double)th[OB3];
+}
+
 // ---- the 2K x 2K step shared by the FP32 gather and the FP64 complement ------
 //
 // Single wave. Given C*, C2, the Grams G1 = W1^T W1 and G2 = W2^T W2 and
@@ -169,15 +197,37 @@ __device__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, con
     }
     if (lane < N) sm->sigma_M[lane] = sg[lane];
     if (lane < K) sm->sigma_new[lane] = sg[lane];
+    // threshold network on the features of this iterate (whole wave)
+    const bool use_mlp = ctrl->stage == STAGE_MAIN && ctrl->learned_on && a.mlp != nullptr;
+    double mlp_o = 0.0;
+    if (use_mlp) {
+        const int r = ctrl->r;
+        const double f = 1e-30;
+        double phi[MLP_IN];
+        phi[0] = (ctrl->k + 1) / MLP_K_FEAT;
+        phi[1] = log(fmax(sg[r], f) / fmax(sg[0], f));
+        phi[2] = log(fmax(ctrl->err, f));
+        phi[3] = log(fmax(sg[0], f) / fmax(sqrt(ctrl->normD2), f));
+        mlp_o = w_mlp(a.mlp, phi);
+    }
     if (lane == 0) {
         const int r = ctrl->r;
         if (ctrl->stage == STAGE_MAIN) {
-            // zeta_{k+1} = beta (sigma_{r+1} + gamma^{k+1} sigma_1)  (Algorithm 1)
+            // zeta_{k+1} = beta (sigma_{r+1} + gamma^{k+1} sigma_1)  (Algorithm 1),
+            // or the learned threshold while it is on (lane 0 has o in mlp_o)
             const int k = ctrl->k;
             const double s1 = sg[0], sr1 = sg[r];
             ctrl->sig1_pt = s1;
             ctrl->sigr1_pt = sr1;
-            ctrl->zeta = ctrl->beta * (sr1 + pow(ctrl->gamma, (double)(k + 1)) * s1);
+            double z = ctrl->beta * (sr1 + pow(ctrl->gamma, (double)(k + 1)) * s1);
+            if (use_mlp) {
+                // learned correction of the paper's threshold: zeta * exp(clip(o))
+                // (a NaN output must not reach fmin / fmax, which would clip it)
+                const double zl = mlp_o == mlp_o ? z * exp(fmin(fmax(mlp_o, -MLP_O_CLIP), MLP_O_CLIP)) : NAN;
+                if (is_finite_pos(zl)) z = zl;
+                else ctrl->learned_on = 0;   // fallback: paper schedule from here on
+            }
+            ctrl->zeta = z;
             ctrl->k = k + 1;
         } else {
             // residual of the leading r directions of the previous block
@@ -326,6 +376,9 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
             ctrl->err = err;
             const int k = ctrl->k;
             ctrl->err_ring[k & 7] = err;
+            // learned schedule: fall back to the paper's once err stops decreasing
+            if (ctrl->learned_on && k >= 1 && !(err < ctrl->err_prev)) ctrl->learned_on = 0;
+            ctrl->err_prev = err;
             if (a.err_hist && k < a.hist_cap) { a.err_hist[k] = err; a.zeta_hist[k] = ctrl->zeta; }
             if (ctrl->want_stop && (err < ctrl->tol || k >= ctrl->max_iter)) {
                 ctrl->done = 1;

@@ -1,0 +1,218 @@
+"""Training of the learned threshold schedule (an extension; the paper fixes
+zeta_{k+1} = beta (sigma_{r+1} + gamma^{k+1} sigma_1), Algorithm 1).
+
+The network maps features of the iterate to a correction of the paper's
+threshold, zeta_k = zeta_paper,k * exp(clip(o_k, -5, 5)) (see include/rpca.h,
+RPCA_FLAG_LEARNED); the untrained network (zero output layer) reproduces the
+paper's schedule. It is trained on synthetic instances with known ground
+truth L = P Q^T by unrolling `steps` iterations with the relaxed threshold
+s(x) = x * logistic((|x| - zeta) / tau) and descending, at every unrolled
+iteration k >= 1, the one-step objective log ||L_{k+1} - L||_F^2 / ||L||_F^2
+with respect to zeta_k (the hand-written adjoint of rpca_relaxed_step), chained
+through d zeta_k / d o_k = zeta_k (inside the clip) and the network's own
+backward kernel, with Adam. The state reached by the unrolled iterations is
+data for the next iteration, not differentiated through (truncated back-
+propagation of one step). tau is annealed as tau_e = tau0 * 0.5^e (relative
+to zeta). All arithmetic runs in the library's kernels; this module only
+sequences the calls.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import inputs as I
+from . import rpca as R
+
+K_FEAT = 15.0       # normalises the iteration index in the features
+FEATURE_FLOOR = 1e-30
+# The loss is formed from inner products in the reduced space, so below about
+# 1e-12 it is at the rounding level of ||L||_F^2: such steps carry no signal.
+LOSS_FLOOR = 1e-12
+
+
+def features(k: int, sigma1: float, sigma_r1: float, err: float, normD: float) -> list[float]:
+    """phi = ((k) / 15, log(sigma_{r+1} / sigma_1), log err, log(sigma_1 / ||D||_F)) for choosing zeta_k."""
+    f = FEATURE_FLOOR
+    return [k / K_FEAT, math.log(max(sigma_r1, f) / max(sigma1, f)), math.log(max(err, f)),
+            math.log(max(sigma1, f) / max(normD, f))]
+
+
+O_CLIP = 5.0
+
+
+def init_theta(seed: int = 0, device="cuda") -> torch.Tensor:
+    """He-style hidden weights, zero biases and a zero output layer: the
+    untrained network outputs o = 0, i.e. the paper's schedule."""
+    g = np.random.default_rng(seed)
+    W1 = g.standard_normal((32, 4)) * math.sqrt(2.0 / 4)
+    W2 = g.standard_normal((32, 32)) * math.sqrt(2.0 / 32)
+    th = np.concatenate([W1.ravel(), np.zeros(32), W2.ravel(), np.zeros(32), np.zeros(32), [0.0]])
+    return torch.tensor(th, dtype=torch.float32, device=device)
+
+
+def save_theta(theta: torch.Tensor, path: str) -> None:
+    np.save(path, theta.detach().cpu().numpy().astype(np.float32), allow_pickle=False)
+
+
+def load_theta(path: str, device="cuda") -> torch.Tensor:
+    a = np.load(path, allow_pickle=False)
+    if a.shape != (R.RPCA_MLP_PARAMS,):
+        raise ValueError(f"{path}: expected {R.RPCA_MLP_PARAMS} parameters")
+    return torch.tensor(a, dtype=torch.float32, device=device)
+
+
+@dataclasses.dataclass
+class Problem:
+    solver: R.Solver
+    P: torch.Tensor
+    Q: torch.Tensor
+    beta: float
+    start: tuple          # state after rpca_init
+
+
+def make_problem(x: I.Instance, dtype=torch.float64, device="cuda") -> Problem:
+    D = torch.as_tensor(x.D, dtype=dtype, device=device)
+    sv = R.Solver(D, x.r, x.beta, x.beta_init, x.gamma, x.mu_in, tol=x.tol, training=True, seed=1)
+    sv.init()
+    return Problem(sv, torch.as_tensor(x.P, dtype=torch.float64, device=device),
+                   torch.as_tensor(x.Q, dtype=torch.float64, device=device), x.beta, sv.get_state())
+
+
+def unroll(pb: Problem, theta: torch.Tensor | None, steps: int, tau_rel: float):
+    """Unrolled relaxed iterations from the initial state. zeta_0 is the
+    initialisation's; zeta_k (k >= 1) comes from the network (theta) or, with
+    theta None, from the paper's schedule. Returns the per-step losses and, for
+    training, the features and d log loss / d o of every network call."""
+    sv = pb.solver
+    sv.put_state(pb.start)
+    normD = sv.state.normD
+    zeta = sv.state.zeta
+    res = sv.relaxed_step(zeta, tau_rel * zeta, pb.P, pb.Q)
+    losses = [res.loss]
+    phis, gos = [], []
+    for k in range(1, steps):
+        zeta = pb.beta * (res.sigma_r1 + sv.params.gamma ** k * res.sigma1)   # Algorithm 1
+        inside = True
+        if theta is not None:
+            phi = torch.tensor([features(k, res.sigma1, res.sigma_r1, res.err, normD)], dtype=torch.float32,
+                               device=theta.device)
+            o = float(R.rpca_mlp_forward(theta, phi)[0])
+            inside = -O_CLIP < o < O_CLIP
+            zeta *= math.exp(min(max(o, -O_CLIP), O_CLIP))
+        res = sv.relaxed_step(zeta, tau_rel * zeta, pb.P, pb.Q)
+        losses.append(res.loss)
+        if theta is not None and res.loss > LOSS_FLOOR and math.isfinite(res.dloss_dzeta):
+            phis.append(phi[0])
+            # d log loss / d o = (d loss / d zeta) zeta / loss inside the clip
+            gos.append(res.dloss_dzeta * zeta / res.loss if inside else 0.0)
+    return losses, phis, gos
+
+
+VALIDATION_IDS = (500, 501, 502, 503)   # training pool instances held out of the training set
+
+
+def solve_stats(theta, ids, dtype=torch.float32):
+    """Real (hard-threshold) solves to tol: (mean iterations, worst recovery
+    error ||L - L_true||_F / ||L_true||_F, all converged)."""
+    its, worst, ok = [], 0.0, True
+    for i in ids:
+        x = I.config_instance(5, i)
+        D = torch.as_tensor(x.D, dtype=dtype, device="cuda")
+        sv = R.Solver(D, x.r, x.beta, x.beta_init, x.gamma, x.mu_in, tol=x.tol, seed=1, learned=theta)
+        info = sv.solve()
+        U, s_, V = sv.L_factors()
+        P = torch.as_tensor(x.P, dtype=torch.float64, device="cuda")
+        Q = torch.as_tensor(x.Q, dtype=torch.float64, device="cuda")
+        # ||U S V^T - P Q^T||_F^2 from r x r products (no dense matrix)
+        a = (U * s_).T @ (U * s_)
+        b = V.T @ V
+        c = P.T @ P
+        d = Q.T @ Q
+        cross = ((U * s_).T @ P) * (V.T @ Q)
+        num = float((a * b).sum() - 2.0 * cross.sum() + (c * d).sum())
+        rec = math.sqrt(max(num, 0.0) / float((c * d).sum()))
+        its.append(info.iterations)
+        worst = max(worst, rec)
+        ok = ok and info.status == R.RPCA_OK
+    return sum(its) / len(its), worst, ok
+
+
+def train(n_instances: int = 32, epochs: int = 12, steps: int = 15, tau0: float = 0.2, lr: float = 3e-4,
+          seed: int = 0, dtype=torch.float64, log=print):
+    """Trains the network on the first n_instances of the training pool
+    (inputs.config_instance(5, i)). After every epoch the network solves the
+    validation instances to tol with the hard threshold; the returned theta is
+    the epoch with the fewest mean iterations among those whose solves all
+    converge with recovery error <= 1e-4 (the untrained network, i.e. the
+    paper's schedule, if none). Returns (theta, history)."""
+    dev = torch.device("cuda")
+    t0 = time.perf_counter()
+    problems = [make_problem(I.config_instance(5, i), dtype, dev) for i in range(n_instances)]
+    log(f"{n_instances} training instances ready in {time.perf_counter() - t0:.1f} s")
+    theta = init_theta(seed, dev)
+    best = theta.clone()
+    best_its, _, _ = solve_stats(None, VALIDATION_IDS)
+    log(f"paper schedule: {best_its:.2f} mean iterations on the validation instances")
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    t = 0
+    hist = []
+    for e in range(epochs):
+        tau_rel = tau0 * 0.5 ** e
+        tot, cnt = 0.0, 0
+        for pb in problems:
+            losses, phis, gos = unroll(pb, theta, steps, tau_rel)
+            tot += sum(math.log(max(l, LOSS_FLOOR)) for l in losses[1:])
+            cnt += len(losses) - 1
+            if not phis:
+                continue
+            phi = torch.stack(phis).contiguous()
+            g = torch.tensor(gos, dtype=torch.float32, device=dev) / len(gos)
+            grad = R.rpca_mlp_backward(theta, phi, g)
+            t += 1
+            R.rpca_mlp_adam(theta, m, v, grad, t, lr)
+        hist.append(tot / max(cnt, 1))
+        its, rec, ok = solve_stats(theta, VALIDATION_IDS)
+        keep = ok and rec <= 1e-4 and its < best_its
+        if keep:
+            best, best_its = theta.clone(), its
+        log(f"epoch {e}: tau/zeta {tau_rel:.4f}  mean log loss {hist[-1]:.4f}  validation: {its:.2f} it, "
+            f"recovery {rec:.1e}{'  (kept)' if keep else ''}  ({time.perf_counter() - t0:.1f} s)")
+    return best, hist
+
+
+def evaluate(theta: torch.Tensor | None, ids, steps: int = 15, tau_rel: float = 1e-6, dtype=torch.float64):
+    """Mean log loss of the unrolled iterations on instances ids of the pool."""
+    tot, cnt = 0.0, 0
+    for i in ids:
+        pb = make_problem(I.config_instance(5, i), dtype)
+        losses, _, _ = unroll(pb, theta, steps, tau_rel)
+        tot += sum(math.log(max(l, LOSS_FLOOR)) for l in losses[1:])
+        cnt += len(losses) - 1
+    return tot / max(cnt, 1)
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="train the learned threshold network")
+    ap.add_argument("--instances", type=int, default=32)
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--steps", type=int, default=15)
+    ap.add_argument("--lr", type=float, default=3e-4)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+    th, hist = train(a.instances, a.epochs, a.steps, lr=a.lr)
+    save_theta(th, a.out)
+    test = list(range(512, 520))
+    print(f"held-out mean log loss: paper {evaluate(None, test, a.steps):.4f}  learned {evaluate(th, test, a.steps):.4f}",
+          flush=True)
+    # real (hard-threshold) solves on the held-out instances
+    for name, theta in (("paper", None), ("learned", th)):
+        its, rec, ok = solve_stats(theta, test)
+        print(f"held-out solves, {name}: {its:.2f} mean iterations, worst recovery {rec:.1e}, all converged {ok}",
+              flush=True)

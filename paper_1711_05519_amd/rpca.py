@@ -28,13 +28,15 @@ RPCA_F64, RPCA_F32 = 0, 1
 RPCA_FLAG_NO_TRIM = 1
 RPCA_FLAG_MIXED = 2
 RPCA_FLAG_TRAINING = 4
+RPCA_FLAG_LEARNED = 8
+RPCA_MLP_PARAMS = 1249
 RPCA_PROF_KINDS = 2
 RPCA_MAX_RANK = 16
 
 EXPORTED = ("rpca_workspace_size", "rpca_init", "rpca_trim", "rpca_step", "rpca_solve",
             "rpca_materialize", "rpca_tangent_products", "rpca_strerror",
             "rpca_last_hip_error", "rpca_version", "rpca_profile_enable", "rpca_profile_read",
-            "rpca_relaxed_step")
+            "rpca_relaxed_step", "rpca_mlp_forward", "rpca_mlp_backward", "rpca_mlp_adam")
 
 
 class RpcaError(RuntimeError):
@@ -53,7 +55,7 @@ class Params(ctypes.Structure):
                 ("mu", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("init_block", ctypes.c_int32),
                 ("init_max_passes", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("seed", ctypes.c_uint64), ("mixed_err", ctypes.c_double)]
+                ("seed", ctypes.c_uint64), ("mixed_err", ctypes.c_double), ("zeta_mlp", ctypes.c_void_p)]
 
 
 class State(ctypes.Structure):
@@ -91,6 +93,10 @@ def _lib():
             "rpca_materialize": [vp, P, S, vp, ctypes.c_int64, vp, ctypes.c_int64, vp, sz, vp],
             "rpca_tangent_products": [vp, P, vp, vp, d, vp, vp, vp, vp, pd, vp, sz, vp],
             "rpca_relaxed_step": [vp, P, S, d, d, vp, vp, ctypes.c_int32, ctypes.POINTER(RelaxResult), vp, sz, vp],
+            "rpca_mlp_forward": [vp, vp, ctypes.c_int32, vp, vp],
+            "rpca_mlp_backward": [vp, vp, vp, ctypes.c_int32, vp, vp],
+            "rpca_mlp_adam": [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, vp],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -171,6 +177,39 @@ def rpca_relaxed_step(D, params, state, zeta, tau, P, Q, ws, stream=None) -> Rel
     return out
 
 
+def _f32(t, n=None):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous float32 device tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} values")
+    return _ptr(t)
+
+
+def rpca_mlp_forward(theta, phi, o=None, stream=None):
+    """o[b] = network(phi[b]); phi: (B, 4) float32 device."""
+    B = phi.shape[0]
+    if o is None:
+        o = torch.empty((B,), dtype=torch.float32, device=phi.device)
+    _check(_lib().rpca_mlp_forward(_f32(theta, RPCA_MLP_PARAMS), _f32(phi, 4 * B), B, _f32(o, B), _stream(stream)),
+           "rpca_mlp_forward")
+    return o
+
+
+def rpca_mlp_backward(theta, phi, grad_o, grad=None, stream=None):
+    B = phi.shape[0]
+    if grad is None:
+        grad = torch.empty((RPCA_MLP_PARAMS,), dtype=torch.float32, device=phi.device)
+    _check(_lib().rpca_mlp_backward(_f32(theta, RPCA_MLP_PARAMS), _f32(phi, 4 * B), _f32(grad_o, B), B,
+                                    _f32(grad, RPCA_MLP_PARAMS), _stream(stream)), "rpca_mlp_backward")
+    return grad
+
+
+def rpca_mlp_adam(theta, m, v, grad, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(_lib().rpca_mlp_adam(_f32(theta, RPCA_MLP_PARAMS), _f32(m, RPCA_MLP_PARAMS), _f32(v, RPCA_MLP_PARAMS),
+                                _f32(grad, RPCA_MLP_PARAMS), int(t), float(lr), float(beta1), float(beta2),
+                                float(eps), _stream(stream)), "rpca_mlp_adam")
+
+
 def rpca_solve(D, params, state, err_hist, zeta_hist, ws, stream=None) -> int:
     """err_hist / zeta_hist: ctypes double arrays (or None)."""
     w, nb = _ws(ws)
@@ -237,7 +276,7 @@ class SolveInfo:
 def make_params(D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: float, mu: float,
                 tol: float = 1e-5, max_iter: int = 100, trim: bool = True, init_block: int = 0,
                 init_max_passes: int = 0, seed: int = 0, mixed: bool = False, mixed_err: float = 0.0,
-                training: bool = False) -> Params:
+                training: bool = False, learned: torch.Tensor | None = None) -> Params:
     if D.dim() != 2 or D.stride(1) != 1:
         raise ValueError("D must be a 2-D row-major tensor with unit column stride")
     if D.dtype == torch.float64:
@@ -250,8 +289,9 @@ def make_params(D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: f
                   beta_init=float(beta_init), gamma=float(gamma), mu=float(mu) if trim else 0.0, tol=float(tol),
                   max_iter=int(max_iter), init_block=int(init_block), init_max_passes=int(init_max_passes),
                   flags=((0 if trim else RPCA_FLAG_NO_TRIM) | (RPCA_FLAG_MIXED if mixed else 0)
-                         | (RPCA_FLAG_TRAINING if training else 0)), seed=int(seed),
-                  mixed_err=float(mixed_err))
+                         | (RPCA_FLAG_TRAINING if training else 0) | (RPCA_FLAG_LEARNED if learned is not None else 0)),
+                  seed=int(seed), mixed_err=float(mixed_err),
+                  zeta_mlp=(_f32(learned, RPCA_MLP_PARAMS) if learned is not None else None))
 
 
 class Solver:
@@ -260,12 +300,13 @@ class Solver:
     def __init__(self, D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: float, mu: float,
                  tol: float = 1e-5, max_iter: int = 100, trim: bool = True, init_block: int = 0,
                  init_max_passes: int = 0, seed: int = 0, mixed: bool = False, mixed_err: float = 0.0,
-                 training: bool = False):
+                 training: bool = False, learned: torch.Tensor | None = None):
         if not D.is_cuda:
             raise ValueError("D must be a device tensor")
         self.D = D
         self.params = make_params(D, r, beta, beta_init, gamma, mu, tol, max_iter, trim, init_block,
-                                  init_max_passes, seed, mixed, mixed_err, training)
+                                  init_max_passes, seed, mixed, mixed_err, training, learned)
+        self._learned = learned   # keeps the parameters alive while the params point at them
         dev = D.device
         m, n = D.shape
         self.U = torch.zeros((m, r), dtype=torch.float64, device=dev)

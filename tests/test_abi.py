@@ -33,8 +33,8 @@ def test_header_and_exports_agree(lib):
 
 def test_struct_layout_matches_header(lib):
     # offsets the C compiler uses for the two structs (natural alignment)
-    assert ctypes.sizeof(R.Params) == 8 * 3 + 4 * 2 + 8 * 5 + 4 * 4 + 8 + 8
-    assert R.Params.mixed_err.offset == ctypes.sizeof(R.Params) - 8
+    assert ctypes.sizeof(R.Params) == 8 * 3 + 4 * 2 + 8 * 5 + 4 * 4 + 8 + 8 + 8
+    assert R.Params.zeta_mlp.offset == ctypes.sizeof(R.Params) - 8
     assert ctypes.sizeof(R.State) == 8 * 3 + 8 * 5 + 4 * 4
 
 
@@ -60,6 +60,7 @@ def test_workspace_size_and_version(lib):
     dict(mu=0.0), dict(max_iter=-1), dict(init_block=2), dict(init_block=17), dict(flags=8),
     dict(beta=float("nan")), dict(tol=float("inf")),
     dict(flags=2, dtype=0), dict(flags=2, dtype=1, mixed_err=float("nan")), dict(flags=4, r=11, m=300, n=300, ldd=300),
+    dict(flags=8), dict(flags=16),
 ])
 def test_invalid_params_rejected(lib, bad):
     with pytest.raises(R.RpcaError) as e:
@@ -113,3 +114,12 @@ def test_relaxed_step_validates_before_launch(lib):
     p2 = _params()   # no training workspace
     assert lib.rpca_relaxed_step(ctypes.byref(d), ctypes.byref(p2), ctypes.byref(st), 1.0, 0.1,
                                  ctypes.byref(d), ctypes.byref(d), 1, ctypes.byref(out), ws, 16, None) == -1
+
+
+def test_mlp_entry_points_validate_before_launch(lib):
+    ws = ctypes.create_string_buffer(64)
+    assert lib.rpca_mlp_forward(None, ws, 1, ws, None) == -1
+    assert lib.rpca_mlp_forward(ws, ws, -1, ws, None) == -1
+    assert lib.rpca_mlp_backward(ws, ws, None, 1, ws, None) == -1
+    assert lib.rpca_mlp_adam(ws, ws, ws, ws, 0, 0.1, 0.9, 0.999, 1e-8, None) == -1
+    assert lib.rpca_mlp_adam(ws, ws, ws, ws, 1, 0.1, 1.0, 0.999, 1e-8, None) == -1

@@ -16,18 +16,21 @@ from paper_1711_05519_amd import inputs as I
 def test_mlp_layout_and_untrained_output():
     assert Lr.N_PARAMS == 1249
     th = Lr.init_theta(0)
-    # zero first-layer weights give o = b3 exactly; init b3 makes softplus(o) = 1
+    # the untrained network outputs o = 0 exactly: the paper's threshold
+    o, _ = Lr.mlp_forward(th, np.array([0.3, -2.0, -1.0, -4.0]))
+    assert o == 0.0
+    assert Lr.zeta_of(o, 7.5) == 7.5
+    # zero first-layer weights give o = b3 exactly, and the correction is clipped
     z = th.copy()
     z[:Lr.N_H * Lr.N_IN] = 0.0
-    z[Lr.N_H * Lr.N_IN:Lr.N_H * Lr.N_IN + Lr.N_H] = 0.0
-    o, _ = Lr.mlp_forward(z, np.array([0.3, -2.0, -1.0, -4.0]))
-    assert o == pytest.approx(np.log(np.e - 1.0), abs=1e-15)
-    assert Lr.zeta_of(o, 0.01, 1000.0) == pytest.approx(10.0, rel=1e-14)
+    z[-1] = 0.7
+    assert Lr.mlp_forward(z, np.array([1.0, 2.0, 3.0, 4.0]))[0] == pytest.approx(0.7, abs=1e-15)
+    assert Lr.zeta_of(40.0, 2.0) == pytest.approx(2.0 * np.exp(5.0), rel=1e-15)
 
 
 def test_mlp_backward_matches_central_differences():
     rng = np.random.default_rng(1)
-    th = Lr.init_theta(3) + 0.05 * rng.standard_normal(Lr.N_PARAMS)
+    th = Lr.init_theta(3) + 0.2 * rng.standard_normal(Lr.N_PARAMS)
     phi = np.array([0.2, -1.5, -2.5, -3.0])
     o, cache = Lr.mlp_forward(th, phi)
     g = Lr.mlp_backward(th, cache, 1.0)
