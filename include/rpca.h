@@ -220,11 +220,12 @@ int rpca_mlp_adam(float *theta, float *m, float *v, const float *grad, int32_t t
  * loop has stopped, which does no work, is not counted. rpca_profile_read
  * waits for the recorded passes and returns, per kind of pass, their summed
  * duration in ms and their number since the previous read, then resets them:
- * stream_ms and stream_launches are arrays of RPCA_PROF_KINDS entries, [0] the
- * passes in the dtype of D, [1] the passes with the BF16 product. Disabling keeps
+ * stream_ms and stream_launches are arrays of RPCA_PROF_KINDS entries: [0] the
+ * loop's passes in the dtype of D, [1] the loop's passes with the BF16
+ * product, [2] the passes of the initialisation (L = 0). Disabling keeps
  * the totals for a final read. Intended for benchmarks: the events add a few
  * microseconds of queue work per pass. */
-#define RPCA_PROF_KINDS 2
+#define RPCA_PROF_KINDS 3
 int rpca_profile_enable(int on);
 int rpca_profile_read(double *stream_ms, int64_t *stream_launches);
 

@@ -91,8 +91,8 @@ struct Profiler {
         int kind;
     };
     std::vector<Rec> pending;
-    double ms[RPCA_PROF_KINDS] = {0.0, 0.0};
-    int64_t launches[RPCA_PROF_KINDS] = {0, 0};
+    double ms[RPCA_PROF_KINDS] = {0.0, 0.0, 0.0};
+    int64_t launches[RPCA_PROF_KINDS] = {0, 0, 0};
 };
 Profiler g_prof;
 
@@ -137,7 +137,7 @@ int stream_launch(const StreamArgs& a, int K, int dtype, bool rebuild, bool mx, 
     else HIP_TRY(launch_stream(a, K, dtype, rebuild, s));
     if (g_prof.on) {
         HIP_TRY(hipEventRecord(e1, s));
-        g_prof.pending.push_back({e0, e1, mx ? 1 : 0});
+        g_prof.pending.push_back({e0, e1, mx ? 1 : (rebuild ? 0 : 2)});
     }
     return RPCA_OK;
 }

@@ -30,7 +30,7 @@ RPCA_FLAG_MIXED = 2
 RPCA_FLAG_TRAINING = 4
 RPCA_FLAG_LEARNED = 8
 RPCA_MLP_PARAMS = 1249
-RPCA_PROF_KINDS = 2
+RPCA_PROF_KINDS = 3
 RPCA_MAX_RANK = 16
 
 EXPORTED = ("rpca_workspace_size", "rpca_init", "rpca_trim", "rpca_step", "rpca_solve",
@@ -240,9 +240,9 @@ def rpca_profile_enable(on: bool) -> None:
 
 
 def rpca_profile_read(kind: int | None = None):
-    """Per kind of streaming pass ([0] dtype of D, [1] BF16 products): summed
-    milliseconds and pass counts since the last read. With kind given, that
-    kind's (ms, count); otherwise the totals over both kinds."""
+    """Per kind of streaming pass ([0] loop, dtype of D; [1] loop, BF16 product;
+    [2] initialisation): summed milliseconds and pass counts since the last
+    read. With kind given, that kind's (ms, count); otherwise the totals."""
     ms = (ctypes.c_double * RPCA_PROF_KINDS)()
     n = (ctypes.c_int64 * RPCA_PROF_KINDS)()
     _check(_lib().rpca_profile_read(ms, n), "rpca_profile_read")
@@ -252,7 +252,8 @@ def rpca_profile_read(kind: int | None = None):
 
 
 def rpca_profile_read_all():
-    """((ms, count) of the dtype passes, (ms, count) of the BF16-product passes)."""
+    """[(ms, count)] of the loop's dtype passes, its BF16-product passes and the
+    initialisation's passes."""
     ms = (ctypes.c_double * RPCA_PROF_KINDS)()
     n = (ctypes.c_int64 * RPCA_PROF_KINDS)()
     _check(_lib().rpca_profile_read(ms, n), "rpca_profile_read")

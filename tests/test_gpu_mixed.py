@@ -132,7 +132,8 @@ def test_mixed_switch_levels():
     # a switch level below the tolerance: every loop body uses BF16 products;
     # the loop still stops by err_k < tol or at the cap, with FP32 residuals
     (ip, Lp, kp), (im, Lm, km) = _plain_and_mixed(x, 1e-12, max_iter=40)
-    assert km[0][1] == im.init_passes          # the initialisation stays FP32
+    assert km[2][1] == im.init_passes          # the initialisation stays FP32
+    assert km[0][1] == 0                        # and every loop pass was a BF16 one
     assert km[1][1] >= im.iterations
     assert np.all(np.isfinite(im.err_hist))
     assert min(im.err_hist) < 1e-2
