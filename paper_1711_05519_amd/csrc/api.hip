@@ -625,34 +625,70 @@ int rpca_solve(const void* D, const rpca_params* p, rpca_state* st, double* err_
     RPCA_TRY(check_state(st));
     Ctx c;
     RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
-    Ctrl ic;
-    RPCA_TRY(run_init(c, D, st, &ic));
-    // switch the control block to the loop: stopping rule on, k = 0
-    Ctrl t;
-    RPCA_TRY(read_ctrl(c, &t));
-    t.want_stop = 1;
-    t.k = 0;
-    t.active = 1;
-    t.done = 0;
+    const int P = c.L.K_init;
+    Ctrl t = base_ctrl(c, STAGE_SIGMA_D, INFINITY, 0, 1.0, 0);
     RPCA_TRY(setup(c, t));
-    // Mixed form: body k + 1 is enqueued once body k - 1 has completed, so
-    // it takes BF16 products while err_{k-1} >= mixed_err (bodies 0 and 1
-    // always do); the first body with err below the level switches every
-    // later body to the FP32 pass. The decision reads err of a fixed body
-    // (the status ring), so it does not depend on timing.
-    bool use_mx = c.mixed;
-    int rc = pipelined_loop(
-        c, p->max_iter + 3,
-        [&]() { return enqueue_body(c, D, p->r, BODY_MAIN, st->U, st->V, st->sigma, true, use_mx); },
-        [&](const HostStatus& hs, int b) {
-            if (use_mx && hs.err_ring[b & 7] < c.mixed_err) use_mx = false;
-            return hs.done != 0;
-        });
+    PanelArgs sa = panel_args(c);
+    sa.seed = p->seed;
+    HIP_TRY(launch_start(sa, P, c.dtype, c.s));
+    // One queue of bodies, one ahead of the host: initialisation bodies until a
+    // completed one reports the stage INIT_DONE (the body queued meanwhile is a
+    // no-op), then the entry update, the switch of the control block (both on
+    // the device) and loop bodies until the stopping rule fires. The host
+    // never waits for the stream in between.
+    // Mixed form: loop body k + 1 is enqueued once loop body k - 1 has
+    // completed, so it takes BF16 products while err_{k-1} >= mixed_err
+    // (bodies 0 and 1 always do); the first body with err below the level
+    // switches every later body to the FP32 pass. The decision reads err of a
+    // fixed body (the status ring), so it does not depend on timing.
+    constexpr int NEV = 4;
+    hipEvent_t ev[NEV];
+    for (int i = 0; i < NEV; ++i) HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    const int max_bodies = 2 * t.init_max_passes + 4 + p->max_iter + 3;
+    bool in_loop = false, use_mx = c.mixed, stopped = false;
+    int loop_first = -1;   // queue index of loop body 0
+    int rc = RPCA_OK;
+    for (int b = 0; b < max_bodies && rc >= 0 && !stopped; ++b) {
+        rc = in_loop ? enqueue_body(c, D, p->r, BODY_MAIN, st->U, st->V, st->sigma, true, use_mx)
+                     : enqueue_body(c, D, P, BODY_INIT, nullptr, nullptr, nullptr, false);
+        if (rc < 0) break;
+        hipError_t e = hipEventRecord(ev[b % NEV], c.s);
+        if (e != hipSuccess) { g_last_hip_error = (int)e; rc = RPCA_EHIP; break; }
+        if (b < 1) continue;
+        e = hipEventSynchronize(ev[(b - 1) % NEV]);
+        if (e != hipSuccess) { g_last_hip_error = (int)e; rc = RPCA_EHIP; break; }
+        HostStatus hs;
+        memcpy(&hs, (const void*)c.dev->status_host, sizeof(hs));
+        if (!in_loop) {
+            if (hs.stage >= STAGE_INIT_DONE) {
+                prof_drop_last();   // body b ran after the stage changed: a no-op
+                // L_0: the leading r columns of the converged block; Trim and bases
+                rc = enqueue_enter(c, c.at<double>(c.L.off_Unew), c.at<double>(c.L.off_Vnew), P,
+                                   c.small()->sigma_new, st->U, st->V, st->sigma);
+                if (rc < 0) break;
+                e = launch_enter_loop(c.ctrl(), c.s);
+                if (e != hipSuccess) { g_last_hip_error = (int)e; rc = RPCA_EHIP; break; }
+                in_loop = true;
+                loop_first = b + 1;
+            }
+        } else if (b - 1 >= loop_first) {
+            const int k_done = b - 1 - loop_first;   // loop body that has completed
+            if (use_mx && hs.err_ring[k_done & 7] < c.mixed_err) use_mx = false;
+            if (hs.done) {
+                prof_drop_last();   // body b was queued after the stop: a no-op
+                stopped = true;
+            }
+        }
+    }
+    hipError_t e = hipStreamSynchronize(c.s);
+    if (e != hipSuccess && rc >= 0) { g_last_hip_error = (int)e; rc = RPCA_EHIP; }
+    for (int i = 0; i < NEV; ++i) (void)hipEventDestroy(ev[i]);
     RPCA_TRY(rc);
     Ctrl fin;
     RPCA_TRY(read_ctrl(c, &fin));
+    if (fin.stage != STAGE_MAIN) return RPCA_EHIP;   // unreachable: the pass cap forces convergence
     fill_state(st, fin);
-    st->init_passes = ic.total_passes;
+    st->init_passes = fin.total_passes;
     const int n = fin.k + 1;
     const int cnt = n < hist_cap ? n : hist_cap;
     if (cnt > 0 && err_hist) HIP_TRY(hipMemcpyAsync(err_hist, c.err_hist(), sizeof(double) * cnt, hipMemcpyDeviceToHost, c.s));

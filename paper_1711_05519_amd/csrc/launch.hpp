@@ -122,6 +122,7 @@ hipError_t launch_update(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_basis(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_start(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, hipStream_t s);
+hipError_t launch_enter_loop(Ctrl* ctrl, hipStream_t s);
 hipError_t launch_relax(const RelaxArgs& a, int dtype, hipStream_t s);
 hipError_t launch_mlp_forward(const float* th, const float* phi, float* o, int B, hipStream_t s);
 hipError_t launch_mlp_backward(const float* th, const float* phi, const float* g, int B, float* grad, hipStream_t s);

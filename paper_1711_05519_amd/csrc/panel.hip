@@ -630,6 +630,19 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_start(PanelArgs a) {
 
 __global__ void k_setup(Ctrl* ctrl, Ctrl init) { if (threadIdx.x == 0 && blockIdx.x == 0) *ctrl = init; }
 
+// The initialisation has converged and the entry update has run: switch the
+// control block to the loop (stopping rule on, k = 0) on the device.
+__global__ void k_enter_loop(Ctrl* ctrl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctrl->stage = STAGE_MAIN;
+        ctrl->want_stop = 1;
+        ctrl->k = 0;
+        ctrl->active = 1;
+        ctrl->done = 0;
+        ctrl->err_prev = 1e300;
+    }
+}
+
 template <typename T>
 __global__ void k_convert(const double* __restrict__ src, T* __restrict__ dst, int64_t count,
                           const double* __restrict__ scale, int K) {
@@ -680,6 +693,11 @@ RPCA_PANEL_LAUNCHER(launch_start, (unsigned)(a.gU + a.gV), PANEL_THREADS)
 
 hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, hipStream_t s) {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, s, ctrl, init);
+    return hipGetLastError();
+}
+
+hipError_t launch_enter_loop(Ctrl* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(k_enter_loop, dim3(1), dim3(64), 0, s, ctrl);
     return hipGetLastError();
 }
 
