@@ -33,6 +33,11 @@ namespace {
 template <typename T> __device__ inline T* tptr(void* p) { return static_cast<T*>(p); }
 template <typename T> __device__ inline const T* tptr(const void* p) { return static_cast<const T*>(p); }
 
+// 16-byte vector of partial-sum values
+template <typename A> struct Vec16;
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
 // ---- row-phase helpers (whole workgroup) --------------------------------------
 
 // y = x A for a row vector x (1 x K) and A (K x K, ld K, LDS)
@@ -53,12 +58,17 @@ __device__ inline void block_load_small(const double* __restrict__ g, double* s)
 }
 
 // Workgroup sum over NR row slots of a (x) b -> dst[t1 * K + t2] (global,
-// K*K entries). Exactly one thread per slot passes writer = true (zero vectors
-// for rows past the end). sa, sb: LDS scratch of NR*K doubles each; every
-// thread of the block must call it.
-template <int K, int NR>
+// K*K entries), for a workgroup of NT threads. Exactly one thread per slot
+// passes writer = true (zero vectors for rows past the end). G adjacent lanes
+// share an output entry: lane g of the group sums slots g, g + G, ..., then a
+// fixed-order DPP reduction over the group (bitwise reproducible). sa, sb: LDS
+// scratch of NR*K doubles each; every thread of the block must call it.
+template <int K, int NR, int NT>
 __device__ void rows_outer_sum(const double (&a)[K], const double (&b)[K], bool writer, int slot, double* sa,
                                double* sb, double* __restrict__ dst) {
+    constexpr int G0 = pow2_floor(NT / (K * K) > 0 ? NT / (K * K) : 1);
+    constexpr int G = G0 > 16 ? 16 : G0;
+    constexpr int STEP = NT / G;   // output entries handled at once
     if (writer) {
 #pragma unroll
         for (int t = 0; t < K; ++t) {
@@ -67,12 +77,15 @@ __device__ void rows_outer_sum(const double (&a)[K], const double (&b)[K], bool 
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+    const int sub = threadIdx.x % G;
+    for (int e0 = threadIdx.x / G; e0 < (K * K + STEP - 1) / STEP * STEP; e0 += STEP) {
+        const int e = e0 < K * K ? e0 : K * K - 1;   // whole groups stay in the loop for the DPP sum
         const int t1 = e / K, t2 = e % K;
         double acc = 0.0;
-#pragma unroll 8
-        for (int r = 0; r < NR; ++r) acc = fma(sa[r * K + t1], sb[r * K + t2], acc);
-        dst[e] = acc;
+#pragma unroll 4
+        for (int r = sub; r < NR; r += G) acc = fma(sa[r * K + t1], sb[r * K + t2], acc);
+        acc = group_sum<G>(acc);
+        if (sub == 0 && e0 < K * K) dst[e] = acc;
     }
     __syncthreads();
 }
@@ -147,7 +160,10 @@ __device__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, con
         Ma[e] = v;
     }
     wave_sync();
-    const int sweeps = wave_jacobi_svd<N>(Ma, Mv, sg, Um, Vm);
+    // columns below a tenth of the dropping level (sigma_dead sigma_1, with
+    // ||M||_F^2 <= N sigma_1^2) need not be rotated against each other
+    const double neg2 = 0.01 * ctrl->sigma_dead * ctrl->sigma_dead / N;
+    const int sweeps = wave_jacobi_svd<N>(Ma, Mv, sg, Um, Vm, neg2);
     // Triplets whose singular value is at the rounding level of the products
     // (sigma_j <= sigma_dead * sigma_1) carry no information about the range
     // of P_T(Z): their vectors are noise and need not be orthogonal to U*, so
@@ -273,9 +289,10 @@ __device__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, con
 
 // ---- kernel 1: gather partial products, C*, residual, stopping rule ----------
 //
-// 1024 threads, GATHER_SPLIT adjacent lanes per row: the lanes of a row sum
-// disjoint subsets of the streaming-pass tiles (one round of loads), then a
-// fixed-order DPP reduction; 128 rows per workgroup, one workgroup per CU.
+// 1024 threads, 128 rows per workgroup (GATHER_SPLIT threads per row slot,
+// the first of which holds the row): the per-tile partials of the
+// workgroup's rows are summed with 16-byte loads of whole tile blocks, then
+// the row products U_f^T Y1 (and Grams) are formed as workgroup partials.
 // The last workgroup sums the per-workgroup partials with all its threads.
 // FP32 (gram_form): also the Grams of Y1 and Y2, and the whole 2K x 2K step in
 // the tail. FP64: only C* and C2; the complement kernel forms W explicitly.
@@ -286,39 +303,76 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     constexpr bool GRAM = sizeof(T) == 4;
     Ctrl* ctrl = a.ctrl;
     if (!body_runs(ctrl, a.body)) return;
-    __shared__ double sa[RPB * K], sb[RPB * K];
     __shared__ int flag;
     const int gU = (a.m + RPB - 1) / RPB;
     const bool uside = (int)blockIdx.x < gU;
     const int slot = threadIdx.x / GATHER_SPLIT, chunk = threadIdx.x % GATHER_SPLIT;
-    const int row = (uside ? blockIdx.x : blockIdx.x - gU) * RPB + slot;
+    const int row0 = (uside ? blockIdx.x : blockIdx.x - gU) * RPB;
+    const int row = row0 + slot;
     const int nrows = uside ? a.m : a.n;
     const int ntiles = uside ? a.n_ct : a.n_rt;
     const Acc* P = tptr<Acc>(uside ? a.P1 : a.P2);
+    // Sum over the tiles of the streaming pass. Per tile, the rows of this
+    // workgroup are one contiguous block of RPB * K values ([row][t]), read as
+    // 16-byte vectors: NWG groups of NV threads each take every NWG-th tile
+    // (up to LR loads in flight), and the groups' sums meet in LDS, summed in
+    // group order (bitwise reproducible).
+    constexpr int VW = 16 / (int)sizeof(Acc);
+    constexpr int FB = RPB * K;
+    constexpr int NV = FB / VW;
+    constexpr int NWG = GATHER_THREADS / NV;
+    constexpr int LR = 8;
+    static_assert(FB % VW == 0 && NWG >= 1, "tile block of the gather");
+    typedef typename Vec16<Acc>::type VecT;
+    // LDS: the groups' tile sums, later the row vectors of the products
+    constexpr int NSH = NWG * FB > 2 * FB ? NWG * FB : 2 * FB;
+    __shared__ double shbuf[NSH];
+    double* gsum = shbuf;
+    double* sa = shbuf;
+    double* sb = shbuf + FB;
+    {
+        const int nval = (nrows - row0 < RPB ? nrows - row0 : RPB) * K;
+        const size_t tstride = (size_t)nrows * K;
+        const int grp = threadIdx.x / NV, vi = threadIdx.x % NV;
+        double acc[VW];
+#pragma unroll
+        for (int j = 0; j < VW; ++j) acc[j] = 0.0;
+        const Acc* base = P + (size_t)row0 * K + (size_t)vi * VW;
+        if (grp < NWG && (vi + 1) * VW <= nval && tstride % VW == 0) {
+            for (int c0 = grp; c0 < ntiles; c0 += LR * NWG) {
+                VecT v[LR];
+#pragma unroll
+                for (int u = 0; u < LR; ++u) {
+                    const int c = c0 + u * NWG;
+                    v[u] = c < ntiles ? *reinterpret_cast<const VecT*>(base + (size_t)c * tstride) : VecT(0);
+                }
+#pragma unroll
+                for (int u = 0; u < LR; ++u)
+#pragma unroll
+                    for (int j = 0; j < VW; ++j) acc[j] += static_cast<double>(v[u][j]);
+            }
+        } else if (grp < NWG) {
+            // ragged end of the block, or a tile stride that is not a whole number of vectors
+            for (int c = grp; c < ntiles; c += NWG)
+#pragma unroll
+                for (int j = 0; j < VW; ++j)
+                    if (vi * VW + j < nval) acc[j] += static_cast<double>(base[(size_t)c * tstride + j]);
+        }
+        if (grp < NWG) {
+#pragma unroll
+            for (int j = 0; j < VW; ++j) gsum[grp * FB + vi * VW + j] = acc[j];
+        }
+    }
+    __syncthreads();
     double y[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) y[t] = 0.0;
-    if (row < nrows) {
-        // up to LR partials per lane and round, all loads in flight at once
-        constexpr int LR0 = 48 / (K * (int)(sizeof(Acc) / 4));
-        constexpr int LR = LR0 < 2 ? 2 : (LR0 > 8 ? 8 : LR0);
-        for (int c0 = chunk; c0 < ntiles; c0 += LR * GATHER_SPLIT) {
-            Acc v[LR][K];
+    if (chunk == 0 && row < nrows) {
+        for (int g = 0; g < NWG; ++g)
 #pragma unroll
-            for (int u = 0; u < LR; ++u) {
-                const int c = c0 + u * GATHER_SPLIT;
-#pragma unroll
-                for (int t = 0; t < K; ++t) v[u][t] = c < ntiles ? P[((size_t)c * nrows + row) * K + t] : Acc(0);
-            }
-#pragma unroll
-            for (int u = 0; u < LR; ++u)
-#pragma unroll
-                for (int t = 0; t < K; ++t) y[t] += static_cast<double>(v[u][t]);
-        }
+            for (int t = 0; t < K; ++t) y[t] += gsum[g * FB + slot * K + t];
     }
-    // reduction over the GATHER_SPLIT adjacent lanes of a row
-#pragma unroll
-    for (int t = 0; t < K; ++t) y[t] = group_sum<GATHER_SPLIT>(y[t]);
+    __syncthreads();   // gsum is reused as sa, sb below
     const bool holder = chunk == 0 && row < nrows;
     double f[K];   // the row of U_f (U side) or V_f (V side)
 #pragma unroll
@@ -336,8 +390,8 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     }
     double* gp = a.gpart + (size_t)blockIdx.x * GPART_STRIDE;
     const bool writer = chunk == 0;   // y and f are zero unless this lane holds a valid row
-    rows_outer_sum<K, RPB>(f, y, writer, slot, sa, sb, gp);      // U_f^T Y1 or V_f^T Y2
-    if (GRAM) rows_outer_sum<K, RPB>(y, y, writer, slot, sa, sb, gp + KMAX * KMAX);
+    rows_outer_sum<K, RPB, GATHER_THREADS>(f, y, writer, slot, sa, sb, gp);      // U_f^T Y1 or V_f^T Y2
+    if (GRAM) rows_outer_sum<K, RPB, GATHER_THREADS>(y, y, writer, slot, sa, sb, gp + KMAX * KMAX);
     if (!last_block_arrives(&ctrl->cnt[CNT_GATHER], &flag)) return;
 
     // ---- last workgroup: all threads sum the partials, then one wave ----
@@ -392,7 +446,7 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
         ctrl->seq += 1;
         ctrl->cnt[CNT_GATHER] = 0;
         go_on = (GRAM && a.mode == GATHER_WITH_SVD && ctrl->active) ? 1 : 0;
-        publish_status(a, ctrl);
+        if (!go_on) publish_status(a, ctrl);   // otherwise the tail publishes
     }
     go_on = __shfl(go_on, 0, WAVE);
     wave_sync();
@@ -450,7 +504,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_complement(PanelArgs a) {
 #pragma unroll
         for (int t = 0; t < K; ++t) { w[t] = ys[t] - vc[t]; a.W2[(size_t)row * K + t] = w[t]; }
     }
-    rows_outer_sum<K, PANEL_THREADS>(w, w, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
+    rows_outer_sum<K, PANEL_THREADS, PANEL_THREADS>(w, w, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
     if (!last_block_arrives(&ctrl->cnt[CNT_COMPLEMENT], &flag)) return;
     __shared__ double gg[2 * K * K], part[PANEL_THREADS];
     double* g1 = gg;
@@ -541,7 +595,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
             }
         }
     }
-    rows_outer_sum<K, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
+    rows_outer_sum<K, PANEL_THREADS, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
     if (!last_block_arrives(&ctrl->cnt[CNT_UPDATE], &flag)) return;
     __shared__ double gg[2 * K * K], rr[K * K], ri[K * K], rr2[K * K], ri2[K * K], part[PANEL_THREADS];
     double* g = gg;
@@ -615,7 +669,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_start(PanelArgs a) {
             gv[t] = static_cast<double>(q);
         }
     }
-    rows_outer_sum<K, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
+    rows_outer_sum<K, PANEL_THREADS, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
     if (!last_block_arrives(&ctrl->cnt[CNT_START], &flag)) return;
     __shared__ double gg[2 * K * K], rr[K * K], ri[K * K], rr2[K * K], ri2[K * K], part[PANEL_THREADS];
     double* g = gg;

@@ -303,7 +303,7 @@ __global__ __launch_bounds__(WAVE) void k_relax_tail(RelaxArgs a) {
         Md[e] = m1;
     }
     wave_sync();
-    const int sweeps = wave_jacobi_svd<N>(Ma, Mv, sg, Um, Vm);   // Um, Vm column-major
+    const int sweeps = wave_jacobi_svd<N, false>(Ma, Mv, sg, Um, Vm);   // Um, Vm column-major
     // M has rank <= 2K: singular values at the rounding level are zero, and
     // their left vectors (undefined in the one-sided method) are dropped; the
     // left null space then enters through the projector term below.

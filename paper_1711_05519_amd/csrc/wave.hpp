@@ -16,6 +16,10 @@ constexpr double JACOBI_EPS = 1e-15;
 // trailing (negligible) columns would otherwise keep rotating on rounding noise.
 constexpr double JACOBI_ABS = 1e-17;
 constexpr int JACOBI_MAX_SWEEPS = 40;
+// Cyclic Jacobi converges quadratically: once every rotation of a sweep had a
+// relative coupling below JACOBI_QUAD, the couplings left after it are of the
+// order JACOBI_QUAD^2 (below JACOBI_EPS), and the confirming sweep is skipped.
+constexpr double JACOBI_QUAD = 1e-8;
 constexpr double CHOL_DEAD_REL = 1e-26;
 
 // ---- single-wave helpers (the last workgroup's tail) ---------------------------
@@ -212,11 +216,15 @@ constexpr int pow2_floor(int x) { int p = 1; while (p * 2 <= x) p *= 2; return p
 // are processed at once, LP lanes per pair, with DPP reductions for the three
 // inner products. A pair is rotated when |a_p . a_q| > JACOBI_EPS ||a_p|| ||a_q||
 // and above the absolute floor JACOBI_ABS ||A||_F^2 (pairs of negligible
-// columns would otherwise rotate on rounding noise). Sweeps stop when no pair
-// was rotated. On return sig[] is descending and Uo/Vo hold the left/right
-// singular vectors as columns (column-major). Returns the sweep count.
-template <int N>
-__device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, double* Vo) {
+// columns would otherwise rotate on rounding noise), unless both columns have
+// ||a||^2 <= neg2 ||A||_F^2 (columns the caller discards: a rotation never
+// raises the smaller norm of a pair). Sweeps stop when no pair was rotated, or
+// (QUAD_STOP) after a sweep whose rotations all had couplings below
+// JACOBI_QUAD; callers that difference the result keep the confirming sweep. On return
+// sig[] is descending and Uo/Vo hold the left/right singular vectors as
+// columns (column-major). Returns the sweep count.
+template <int N, bool QUAD_STOP = true>
+__device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, double* Vo, double neg2 = 0.0) {
     static_assert(N % 2 == 0 && N <= 2 * KMAX, "even N up to 2*KMAX");
     constexpr int NP = N / 2;
     constexpr int LP0 = pow2_floor(WAVE / NP);
@@ -230,11 +238,12 @@ __device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, do
     }
     for (int off = 32; off > 0; off >>= 1) fro += __shfl_xor(fro, off, WAVE);
     const double floor_abs = JACOBI_ABS * fro;
+    const double floor_neg = neg2 * fro;
     wave_sync();
     const int q = lane / LP, g = lane % LP;
     int sweep = 0;
     for (; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
-        bool rotated = false;
+        bool rotated = false, large = false;
         for (int rd = 0; rd < N - 1; ++rd) {
             if (q < NP) {
                 const int a = (q == 0) ? 0 : ((q - 1 + rd) % (N - 1)) + 1;
@@ -256,15 +265,19 @@ __device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, do
                 al = group_sum<LP>(al);
                 be = group_sum<LP>(be);
                 ga = group_sum<LP>(ga);
-                if (ga * ga > (JACOBI_EPS * JACOBI_EPS) * (al * be) && fabs(ga) > floor_abs) {
-                    // tangent of the rotation angle: the root of smaller modulus of
-                    // t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga), written
-                    // without forming zeta
+                if (ga * ga > (JACOBI_EPS * JACOBI_EPS) * (al * be) && fabs(ga) > floor_abs &&
+                    fmax(al, be) > floor_neg) {
+                    large = large || ga * ga > (JACOBI_QUAD * JACOBI_QUAD) * (al * be);
+                    // rotation by theta, |theta| <= pi/4, tan 2 theta = 2 ga / (be - al):
+                    // with h = sqrt((be - al)^2 + 4 ga^2), cos 2 theta = |be - al| / h,
+                    // c = sqrt((1 + cos 2 theta) / 2), s = sign(be - al) ga / (h c);
+                    // two reciprocal square roots, no division
                     const double dl = be - al;
-                    const double hyp = sqrt(fma(dl, dl, 4.0 * ga * ga));
-                    const double t = (dl >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(dl) + hyp);
-                    const double c = rsqrt(fma(t, t, 1.0));
-                    const double s = c * t;
+                    const double rh = rsqrt(fma(dl, dl, 4.0 * ga * ga));
+                    const double c2 = fma(0.5 * fabs(dl), rh, 0.5);
+                    const double ic = rsqrt(c2);
+                    const double c = c2 * ic;
+                    const double s = (dl >= 0.0 ? ga : -ga) * rh * ic;
 #pragma unroll
                     for (int u = 0; u < E; ++u) {
                         const int e = g + LP * u;
@@ -281,6 +294,7 @@ __device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, do
             wave_sync();
         }
         if (!__any(rotated)) break;
+        if (QUAD_STOP && !__any(large)) { ++sweep; break; }
     }
     // column norms, ranks (descending, ties by index), normalised outputs
     if (lane < N) {
