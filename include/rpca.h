@@ -25,7 +25,10 @@
  *   ordered on it. Calls that report host-visible results (the scalars of
  *   rpca_state, histories) synchronise with the stream before returning.
  * - One call at a time per workspace; calls sharing a workspace must not
- *   overlap. Calls with distinct workspaces may run concurrently.
+ *   overlap. Calls with distinct workspaces may run concurrently; at most 32
+ *   rpca_init / rpca_solve calls may be in flight per device (each holds a
+ *   small slot of host-visible status memory; beyond that they return
+ *   RPCA_EHIP with rpca_last_hip_error() = hipErrorOutOfMemory).
  * - Return value: RPCA_OK (0) or RPCA_MAXITER (1) on success, a negative
  *   RPCA_E* code on failure. Arguments are validated before any launch; a
  *   failed validation leaves every output untouched.

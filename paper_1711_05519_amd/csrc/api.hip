@@ -10,6 +10,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
+#include <chrono>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -42,12 +44,17 @@ constexpr int MAX_DEVICES = 64;
         if (s_ < 0) return s_;      \
     } while (0)
 
+// Status slots in mapped, coherent host memory, one per call in flight on a
+// device that runs a queue of bodies (rpca_init, rpca_solve).
+constexpr int STATUS_SLOTS = 32;
+
 struct DeviceInfo {
     bool checked = false;
     bool ok = false;
     int cus = 256;
-    HostStatus* status_host = nullptr;
+    HostStatus* status_host = nullptr;   // STATUS_SLOTS slots
     HostStatus* status_dev = nullptr;
+    uint32_t slots_used = 0;             // bit i: slot i belongs to a call (g_dev_mutex)
 };
 std::mutex g_dev_mutex;
 DeviceInfo g_dev[MAX_DEVICES];
@@ -66,8 +73,8 @@ int device_info(DeviceInfo** out) {
         d.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
         if (d.ok) {
             void* h = nullptr;
-            HIP_TRY(hipHostMalloc(&h, sizeof(HostStatus), hipHostMallocMapped | hipHostMallocCoherent));
-            memset(h, 0, sizeof(HostStatus));
+            HIP_TRY(hipHostMalloc(&h, sizeof(HostStatus) * STATUS_SLOTS, hipHostMallocMapped | hipHostMallocCoherent));
+            memset(h, 0, sizeof(HostStatus) * STATUS_SLOTS);
             void* dp = nullptr;
             HIP_TRY(hipHostGetDevicePointer(&dp, h, 0));
             d.status_host = static_cast<HostStatus*>(h);
@@ -79,7 +86,46 @@ int device_info(DeviceInfo** out) {
     return RPCA_OK;
 }
 
+// A status slot held for the duration of one call.
+class StatusSlot {
+public:
+    explicit StatusSlot(DeviceInfo* d) : d_(d) {
+        std::lock_guard<std::mutex> lock(g_dev_mutex);
+        for (int i = 0; i < STATUS_SLOTS; ++i) {
+            if (!(d_->slots_used & (1u << i))) {
+                d_->slots_used |= 1u << i;
+                idx_ = i;
+                memset(d_->status_host + i, 0, sizeof(HostStatus));
+                break;
+            }
+        }
+    }
+    ~StatusSlot() {
+        if (idx_ < 0) return;
+        std::lock_guard<std::mutex> lock(g_dev_mutex);
+        d_->slots_used &= ~(1u << idx_);
+    }
+    StatusSlot(const StatusSlot&) = delete;
+    StatusSlot& operator=(const StatusSlot&) = delete;
+    bool ok() const { return idx_ >= 0; }
+    HostStatus* host() const { return d_->status_host + idx_; }
+    HostStatus* dev() const { return d_->status_dev + idx_; }
+
+private:
+    DeviceInfo* d_;
+    int idx_ = -1;
+};
+
 bool is_fin(double x) { return isfinite(x) != 0; }
+
+#define RPCA_TAKE_SLOT(slot, c)                                       \
+    StatusSlot slot((c).dev);                                         \
+    if (!slot.ok()) {                                                 \
+        g_last_hip_error = (int)hipErrorOutOfMemory;                  \
+        return RPCA_EHIP;                                             \
+    }                                                                 \
+    (c).st_host = slot.host();                                        \
+    (c).st_dev = slot.dev()
 
 // ---- measurement: events around every streaming pass ---------------------------
 struct Profiler {
@@ -283,6 +329,8 @@ struct Ctx {
     int dtype;
     bool mixed;          // RPCA_FLAG_MIXED: BF16-product bodies while err_k >= mixed_err
     double mixed_err;
+    HostStatus* st_host = nullptr;   // the call's status slot (queues of bodies only)
+    HostStatus* st_dev = nullptr;
     Ctrl* ctrl() const { return reinterpret_cast<Ctrl*>(ws + L.off_ctrl); }
     Small* small() const { return reinterpret_cast<Small*>(ws + L.off_small); }
     double* err_hist() const { return reinterpret_cast<double*>(ws + L.off_hist); }
@@ -405,7 +453,8 @@ PanelArgs panel_args(const Ctx& c, const Geo& g = Geo{0, 1}) {
     a.Vf = c.ws + c.L.off_Vf;
     a.AL = c.ws + c.L.off_AL;
     a.BL = c.ws + c.L.off_BL;
-    a.host_status = c.dev->status_dev;
+    a.host_status = c.st_dev;
+    a.body_id = 0;
     a.body = BODY_ANY;
     a.mlp = (c.p->flags & RPCA_FLAG_LEARNED) ? c.p->zeta_mlp : nullptr;
     return a;
@@ -419,7 +468,7 @@ int setup(const Ctx& c, const Ctrl& t) {
 // One loop body. FP32: stream pass, gather (with the 2r x 2r step), update.
 // FP64: stream pass, gather, complement (explicit W), update.
 int enqueue_body(const Ctx& c, const void* D, int K, int body, double* state_U, double* state_V,
-                 double* state_sigma, bool with_hist, bool mx = false) {
+                 double* state_sigma, bool with_hist, bool mx = false, int32_t body_id = 0) {
     const bool rebuild = body != BODY_INIT;
     const bool fp32 = c.dtype == RPCA_F32;
     const Geo g = geo_for(c, K, rebuild, mx);
@@ -437,6 +486,7 @@ int enqueue_body(const Ctx& c, const void* D, int K, int body, double* state_U, 
     if (!fp32) HIP_TRY(launch_complement(pa, K, c.dtype, c.s));
     PanelArgs ua = pa;
     ua.mode = UPDATE_FROM_M;
+    ua.body_id = body_id;
     ua.S2U = fp32 ? pa.Y1 : pa.W1;
     ua.S2V = fp32 ? pa.Y2 : pa.W2;
     if (body == BODY_INIT) {
@@ -469,26 +519,52 @@ int enqueue_enter(const Ctx& c, const double* srcU, const double* srcV, int64_t 
     return RPCA_OK;
 }
 
-// Runs queued bodies until `finished(status, b)`, called once body b has
-// completed (b = 0, 1, ...); keeps one body queued ahead.
+inline void cpu_relax() { __builtin_ia32_pause(); }
+
+// Waits until the completion record of body `id` is in the call's status slot
+// (written by the body's last kernel). A stream that drains without it, or
+// reports an error, ends the wait with RPCA_EHIP.
+int wait_record(const Ctx& c, int32_t id, BodyRecord* out) {
+    const volatile BodyRecord* r = &c.st_host->body[id & (BODY_RING - 1)];
+    auto last = std::chrono::steady_clock::now();
+    for (uint32_t spin = 1; r->id != id; ++spin) {
+        cpu_relax();
+        if ((spin & 1023u) != 0) continue;
+        const auto now = std::chrono::steady_clock::now();
+        if (now - last < std::chrono::microseconds(500)) continue;
+        last = now;
+        const hipError_t e = hipStreamQuery(c.s);
+        if (e == hipSuccess) {
+            if (r->id == id) break;
+            return RPCA_EHIP;   // the queue drained without the record
+        }
+        if (e != hipErrorNotReady) {
+            g_last_hip_error = (int)e;
+            return RPCA_EHIP;
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    out->id = r->id;
+    out->stage = r->stage;
+    out->done = r->done;
+    out->k = r->k;
+    out->err = r->err;
+    return RPCA_OK;
+}
+
+// Runs queued bodies until `finished(record, b)`, called once body b has
+// completed (b = 0, 1, ...; body b has id b + 1); keeps one body queued ahead.
 template <typename Enq, typename Fin>
 int pipelined_loop(const Ctx& c, int max_bodies, Enq enqueue, Fin finished) {
-    constexpr int NEV = 4;
-    hipEvent_t ev[NEV];
-    for (int i = 0; i < NEV; ++i) HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
     int rc = RPCA_OK;
-    int b = 0;
-    for (; b < max_bodies; ++b) {
-        rc = enqueue();
+    for (int b = 0; b < max_bodies; ++b) {
+        rc = enqueue(b + 1);
         if (rc < 0) break;
-        hipError_t e = hipEventRecord(ev[b % NEV], c.s);
-        if (e != hipSuccess) { g_last_hip_error = (int)e; rc = RPCA_EHIP; break; }
         if (b >= 1) {
-            e = hipEventSynchronize(ev[(b - 1) % NEV]);
-            if (e != hipSuccess) { g_last_hip_error = (int)e; rc = RPCA_EHIP; break; }
-            HostStatus st;
-            memcpy(&st, (const void*)c.dev->status_host, sizeof(st));
-            if (finished(st, b - 1)) {
+            BodyRecord rec;
+            rc = wait_record(c, b, &rec);
+            if (rc < 0) break;
+            if (finished(rec, b - 1)) {
                 prof_drop_last();   // body b was queued after the stop: a no-op
                 break;
             }
@@ -496,7 +572,6 @@ int pipelined_loop(const Ctx& c, int max_bodies, Enq enqueue, Fin finished) {
     }
     hipError_t e = hipStreamSynchronize(c.s);
     if (e != hipSuccess && rc >= 0) { g_last_hip_error = (int)e; rc = RPCA_EHIP; }
-    for (int i = 0; i < NEV; ++i) (void)hipEventDestroy(ev[i]);
     return rc;
 }
 
@@ -518,8 +593,8 @@ int run_init(const Ctx& c, const void* D, rpca_state* st, Ctrl* ctrl_out) {
     const int max_bodies = 2 * t.init_max_passes + 4;
     int rc = pipelined_loop(
         c, max_bodies,
-        [&]() { return enqueue_body(c, D, P, BODY_INIT, nullptr, nullptr, nullptr, false); },
-        [&](const HostStatus& hs, int) { return hs.stage >= STAGE_INIT_DONE; });
+        [&](int32_t id) { return enqueue_body(c, D, P, BODY_INIT, nullptr, nullptr, nullptr, false, false, id); },
+        [&](const BodyRecord& r, int) { return r.stage >= STAGE_INIT_DONE; });
     RPCA_TRY(rc);
     Ctrl now;
     RPCA_TRY(read_ctrl(c, &now));
@@ -608,6 +683,7 @@ int rpca_init(const void* D, const rpca_params* p, rpca_state* st, void* ws, siz
     RPCA_TRY(check_state(st));
     Ctx c;
     RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
+    RPCA_TAKE_SLOT(slot, c);
     Ctrl ic;
     RPCA_TRY(run_init(c, D, st, &ic));
     // err_0 from one threshold pass: S_0 = T_zeta_0(D - L_0)
@@ -625,6 +701,7 @@ int rpca_solve(const void* D, const rpca_params* p, rpca_state* st, double* err_
     RPCA_TRY(check_state(st));
     Ctx c;
     RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
+    RPCA_TAKE_SLOT(slot, c);
     const int P = c.L.K_init;
     Ctrl t = base_ctrl(c, STAGE_SIGMA_D, INFINITY, 0, 1.0, 0);
     RPCA_TRY(setup(c, t));
@@ -640,25 +717,22 @@ int rpca_solve(const void* D, const rpca_params* p, rpca_state* st, double* err_
     // completed, so it takes BF16 products while err_{k-1} >= mixed_err
     // (bodies 0 and 1 always do); the first body with err below the level
     // switches every later body to the FP32 pass. The decision reads err of a
-    // fixed body (the status ring), so it does not depend on timing.
-    constexpr int NEV = 4;
-    hipEvent_t ev[NEV];
-    for (int i = 0; i < NEV; ++i) HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    // fixed body (its completion record), so it does not depend on timing.
+    // Body b has id b + 1; the host polls the records instead of queueing
+    // events, which would add a marker between the bodies.
     const int max_bodies = 2 * t.init_max_passes + 4 + p->max_iter + 3;
     bool in_loop = false, use_mx = c.mixed, stopped = false;
     int loop_first = -1;   // queue index of loop body 0
     int rc = RPCA_OK;
     for (int b = 0; b < max_bodies && rc >= 0 && !stopped; ++b) {
-        rc = in_loop ? enqueue_body(c, D, p->r, BODY_MAIN, st->U, st->V, st->sigma, true, use_mx)
-                     : enqueue_body(c, D, P, BODY_INIT, nullptr, nullptr, nullptr, false);
+        rc = in_loop ? enqueue_body(c, D, p->r, BODY_MAIN, st->U, st->V, st->sigma, true, use_mx, b + 1)
+                     : enqueue_body(c, D, P, BODY_INIT, nullptr, nullptr, nullptr, false, false, b + 1);
         if (rc < 0) break;
-        hipError_t e = hipEventRecord(ev[b % NEV], c.s);
-        if (e != hipSuccess) { g_last_hip_error = (int)e; rc = RPCA_EHIP; break; }
         if (b < 1) continue;
-        e = hipEventSynchronize(ev[(b - 1) % NEV]);
-        if (e != hipSuccess) { g_last_hip_error = (int)e; rc = RPCA_EHIP; break; }
-        HostStatus hs;
-        memcpy(&hs, (const void*)c.dev->status_host, sizeof(hs));
+        BodyRecord hs;
+        rc = wait_record(c, b, &hs);
+        if (rc < 0) break;
+        hipError_t e = hipSuccess;
         if (!in_loop) {
             if (hs.stage >= STAGE_INIT_DONE) {
                 prof_drop_last();   // body b ran after the stage changed: a no-op
@@ -673,7 +747,7 @@ int rpca_solve(const void* D, const rpca_params* p, rpca_state* st, double* err_
             }
         } else if (b - 1 >= loop_first) {
             const int k_done = b - 1 - loop_first;   // loop body that has completed
-            if (use_mx && hs.err_ring[k_done & 7] < c.mixed_err) use_mx = false;
+            if (use_mx && hs.err < c.mixed_err) use_mx = false;   // hs.err = err_{k_done}
             if (hs.done) {
                 prof_drop_last();   // body b was queued after the stop: a no-op
                 stopped = true;
@@ -682,7 +756,6 @@ int rpca_solve(const void* D, const rpca_params* p, rpca_state* st, double* err_
     }
     hipError_t e = hipStreamSynchronize(c.s);
     if (e != hipSuccess && rc >= 0) { g_last_hip_error = (int)e; rc = RPCA_EHIP; }
-    for (int i = 0; i < NEV; ++i) (void)hipEventDestroy(ev[i]);
     RPCA_TRY(rc);
     Ctrl fin;
     RPCA_TRY(read_ctrl(c, &fin));

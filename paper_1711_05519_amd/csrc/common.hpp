@@ -49,15 +49,19 @@ enum CounterSlot : int {
     CNT_COUNT = 8,
 };
 
-// Host-visible status written by the gather kernel into mapped pinned memory.
-struct HostStatus {
-    int32_t seq;         // number of gather kernels completed
-    int32_t done;        // loop finished
+// Completion record of one queued body, written into mapped host memory by
+// the body's last kernel (ring slot id & (BODY_RING - 1)); id is written last.
+struct BodyRecord {
+    int32_t id;          // body id given by the host (> 0)
     int32_t stage;
+    int32_t done;        // loop finished
     int32_t k;
-    double err;
-    double zeta;
-    double err_ring[8];  // err_k of loop body k in slot k & 7
+    double err;          // err of the state the body started from (loop bodies)
+};
+constexpr int BODY_RING = 8;
+// One per call in flight on a device (a pool in mapped, coherent host memory).
+struct HostStatus {
+    BodyRecord body[BODY_RING];
 };
 
 // Control block at the start of the workspace (device memory).
@@ -90,7 +94,6 @@ struct Ctrl {
     double resid2;       // last residual sum (sum over |x| <= zeta of x^2)
     double sigma_dead;   // relative size below which a singular triplet of M is dropped
     double max_abs_D;    // max |D_ij| (from the init passes, where L = 0)
-    double err_ring[8];  // err_k of loop body k in slot k & 7 (published to the host)
     double err_prev;     // err_{k-1} (fallback test of the learned schedule)
     int32_t learned_on;  // 1 while zeta_{k+1} comes from the threshold network
     int32_t pad2_;

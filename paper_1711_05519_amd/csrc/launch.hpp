@@ -71,7 +71,8 @@ struct PanelArgs {
     double* outU; double* outV;
     // histories and host status
     double* err_hist; double* zeta_hist; int32_t hist_cap;
-    HostStatus* host_status;
+    HostStatus* host_status;  // the call's status slot (device view), or null
+    int32_t body_id;          // update kernel: > 0 writes the body's completion record
     uint64_t seed;
     const float* mlp;         // threshold network parameters (learned schedule) or null
     int32_t mode;             // kernel-specific

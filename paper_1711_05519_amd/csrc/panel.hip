@@ -90,21 +90,6 @@ __device__ void rows_outer_sum(const double (&a)[K], const double (&b)[K], bool 
     __syncthreads();
 }
 
-__device__ inline void publish_status(const PanelArgs& a, const Ctrl* c) {
-    if (a.host_status) {
-        HostStatus st;
-        st.seq = c->seq;
-        st.done = c->done;
-        st.stage = c->stage;
-        st.k = c->k;
-        st.err = c->err;
-        st.zeta = c->zeta;
-        for (int i = 0; i < 8; ++i) st.err_ring[i] = c->err_ring[i];
-        *a.host_status = st;
-        __threadfence_system();
-    }
-}
-
 __device__ inline bool is_finite_pos(double x) { return x > 0.0 && x < 1e300; }
 constexpr double MLP_O_CLIP = 5.0;   // the correction exp(o) stays within e^-5 .. e^5
 
@@ -160,9 +145,10 @@ __device__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, con
         Ma[e] = v;
     }
     wave_sync();
-    // columns below a tenth of the dropping level (sigma_dead sigma_1, with
-    // ||M||_F^2 <= N sigma_1^2) need not be rotated against each other
-    const double neg2 = 0.01 * ctrl->sigma_dead * ctrl->sigma_dead / N;
+    // Pairs of columns with ||a||^2 <= sigma_dead^2 ||M||_F^2 / N <= (sigma_dead
+    // sigma_1)^2 are not rotated against each other: both end below the
+    // dropping level below, and such a rotation moves no other column.
+    const double neg2 = ctrl->sigma_dead * ctrl->sigma_dead / N;
     const int sweeps = wave_jacobi_svd<N>(Ma, Mv, sg, Um, Vm, neg2);
     // Triplets whose singular value is at the rounding level of the products
     // (sigma_j <= sigma_dead * sigma_1) carry no information about the range
@@ -282,7 +268,6 @@ __device__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, con
             }
         }
         ctrl->jacobi_sweeps += sweeps;
-        publish_status(a, ctrl);
     }
     wave_sync();
 }
@@ -429,7 +414,6 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
             const double err = sqrt(rs / ctrl->normD2);
             ctrl->err = err;
             const int k = ctrl->k;
-            ctrl->err_ring[k & 7] = err;
             // learned schedule: fall back to the paper's once err stops decreasing
             if (ctrl->learned_on && k >= 1 && !(err < ctrl->err_prev)) ctrl->learned_on = 0;
             ctrl->err_prev = err;
@@ -446,7 +430,6 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
         ctrl->seq += 1;
         ctrl->cnt[CNT_GATHER] = 0;
         go_on = (GRAM && a.mode == GATHER_WITH_SVD && ctrl->active) ? 1 : 0;
-        if (!go_on) publish_status(a, ctrl);   // otherwise the tail publishes
     }
     go_on = __shfl(go_on, 0, WAVE);
     wave_sync();
@@ -526,6 +509,18 @@ template <typename T, int K>
 __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
     Ctrl* ctrl = a.ctrl;
     const bool from_m = a.mode == UPDATE_FROM_M;
+    if (a.body_id > 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        // completion record of this body for the host (the control block is
+        // final: the gather and complement kernels of the body have ended)
+        volatile BodyRecord* rec = &a.host_status->body[a.body_id & (BODY_RING - 1)];
+        rec->stage = ctrl->stage;
+        rec->done = ctrl->done;
+        rec->k = ctrl->k;
+        rec->err = ctrl->err;
+        __threadfence_system();
+        rec->id = a.body_id;
+        __threadfence_system();
+    }
     if (from_m && !ctrl->active) return;
     __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K];
     __shared__ double e1[K * K], e2[K * K], sig[K];
