@@ -36,6 +36,12 @@ if ROOT not in sys.path:
 
 METRIC = "s to rel. err ≤1e-5 and HBM GB/s per step, m=n=10000 r=5: learned/mixed vs plain"
 HBM_PEAK_GBPS = 8000.0
+# HBM bytes per launch of the loop's streaming pass at this workload, from the
+# FETCH_SIZE / WRITE_SIZE counter runs scaled by a device copy of known size
+# (profiles/k_stream_f32_r5_traffic.md); valid while the kernel source is the
+# one measured.
+TRAFFIC_BYTES = 446.8e6
+TRAFFIC_SOURCE = ("paper_1711_05519_amd/csrc/stream.hip", "9d3420adb18d730c")
 
 
 def parse():
@@ -49,8 +55,18 @@ def parse():
     ap.add_argument("--init-block", type=int, default=0, help="block width of the initialisation (0: library default)")
     ap.add_argument("--forms", default="plain,mixed,learned,learned+mixed",
                     help="comma-separated forms to time (the headline form, learned, is always included)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed work, one device copy of D (4 m n bytes): the reference kernel that "
+                         "scales the HBM traffic counters")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
+
+
+def traffic_bytes():
+    import hashlib
+    path, prefix = TRAFFIC_SOURCE
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return TRAFFIC_BYTES if hashlib.sha256(f.read()).hexdigest().startswith(prefix) else None
 
 
 def log(args, *a):
@@ -210,9 +226,15 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": None,
+            "traffic": traffic_bytes(),
         },
     }
+    if args.copy_probe:
+        torch.cuda.synchronize()
+        E = D.clone()
+        torch.cuda.synchronize()
+        log(args, f"copy probe: {E.numel() * E.element_size()} bytes copied")
+        del E
     if args.cpu_baseline == "on":
         log(args, "timing the CPU oracle sample ...")
         # the oracle follows the paper's schedule: extrapolate to the plain form's iterations
