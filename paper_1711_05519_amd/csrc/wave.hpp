@@ -16,9 +16,10 @@ constexpr double JACOBI_EPS = 1e-15;
 // trailing (negligible) columns would otherwise keep rotating on rounding noise.
 constexpr double JACOBI_ABS = 1e-17;
 constexpr int JACOBI_MAX_SWEEPS = 40;
-// Cyclic Jacobi converges quadratically: once every rotation of a sweep had a
-// relative coupling below JACOBI_QUAD, the couplings left after it are of the
-// order JACOBI_QUAD^2 (below JACOBI_EPS), and the confirming sweep is skipped.
+// Cyclic Jacobi converges quadratically: once every rotation of a sweep was by
+// an angle below JACOBI_QUAD (the angle is the coupling over the gap of the
+// pair), the angles a further sweep would take are of the order
+// JACOBI_QUAD^2, and the confirming sweep is skipped.
 constexpr double JACOBI_QUAD = 1e-8;
 constexpr double CHOL_DEAD_REL = 1e-26;
 
@@ -219,7 +220,7 @@ constexpr int pow2_floor(int x) { int p = 1; while (p * 2 <= x) p *= 2; return p
 // columns would otherwise rotate on rounding noise), unless both columns have
 // ||a||^2 <= neg2 ||A||_F^2 (columns the caller discards: a rotation never
 // raises the smaller norm of a pair). Sweeps stop when no pair was rotated, or
-// (QUAD_STOP) after a sweep whose rotations all had couplings below
+// (QUAD_STOP) after a sweep whose rotation angles were all below
 // JACOBI_QUAD; callers that difference the result keep the confirming sweep. On return
 // sig[] is descending and Uo/Vo hold the left/right singular vectors as
 // columns (column-major). Returns the sweep count.
@@ -267,7 +268,7 @@ __device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, do
                 ga = group_sum<LP>(ga);
                 if (ga * ga > (JACOBI_EPS * JACOBI_EPS) * (al * be) && fabs(ga) > floor_abs &&
                     fmax(al, be) > floor_neg) {
-                    large = large || ga * ga > (JACOBI_QUAD * JACOBI_QUAD) * (al * be);
+
                     // rotation by theta, |theta| <= pi/4, tan 2 theta = 2 ga / (be - al):
                     // with h = sqrt((be - al)^2 + 4 ga^2), cos 2 theta = |be - al| / h,
                     // c = sqrt((1 + cos 2 theta) / 2), s = sign(be - al) ga / (h c);
@@ -278,6 +279,7 @@ __device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, do
                     const double ic = rsqrt(c2);
                     const double c = c2 * ic;
                     const double s = (dl >= 0.0 ? ga : -ga) * rh * ic;
+                    large = large || fabs(s) > JACOBI_QUAD;
 #pragma unroll
                     for (int u = 0; u < E; ++u) {
                         const int e = g + LP * u;
