@@ -40,7 +40,7 @@ HBM_PEAK_GBPS = 8000.0
 # FETCH_SIZE / WRITE_SIZE counter runs scaled by a device copy of known size
 # (profiles/k_stream_f32_r5_traffic.md); valid while the kernel source is the
 # one measured.
-TRAFFIC_BYTES = 446.8e6
+TRAFFIC_BYTES = {2: 446.8e6}   # by workload configuration
 TRAFFIC_SOURCE = ("paper_1711_05519_amd/csrc/stream.hip", "9d3420adb18d730c")
 
 
@@ -62,11 +62,12 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_bytes():
+def traffic_bytes(config: int):
     import hashlib
     path, prefix = TRAFFIC_SOURCE
     with open(os.path.join(ROOT, path), "rb") as f:
-        return TRAFFIC_BYTES if hashlib.sha256(f.read()).hexdigest().startswith(prefix) else None
+        same = hashlib.sha256(f.read()).hexdigest().startswith(prefix)
+    return TRAFFIC_BYTES.get(config) if same else None
 
 
 def log(args, *a):
@@ -226,7 +227,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": traffic_bytes(),
+            "traffic": traffic_bytes(args.config),
         },
     }
     if args.copy_probe:
