@@ -158,6 +158,24 @@ int rpca_solve(const void *D, const rpca_params *p, rpca_state *st,
                double *err_hist, double *zeta_hist, int32_t hist_cap,
                void *ws, size_t ws_bytes, void *stream);
 
+/* Several independent solves advanced together from one host thread (a
+ * batch of instances): instance i is exactly rpca_solve(D[i], p[i], st[i],
+ * err_hist[i], zeta_hist[i], hist_cap, ws[i], ws_bytes[i], streams[i %
+ * n_streams]), with its own workspace, and the host follows every instance's
+ * queue of bodies without blocking on any of them, so the bodies of up to
+ * n_streams instances run concurrently (one instance per stream at a time, in
+ * index order). Not part of the paper: a throughput form for many small
+ * problems. err_hist / zeta_hist may be NULL (or hold NULL entries).
+ * status[i] receives instance i's rpca_solve status. Returns RPCA_OK, or the
+ * first negative status of an instance (the others still run), or RPCA_EINVAL
+ * for bad arguments (nothing run). 1 <= n_streams <= RPCA_MANY_MAX_STREAMS;
+ * the streams must be distinct. */
+#define RPCA_MANY_MAX_STREAMS 16
+int rpca_solve_many(int32_t count, const void *const *D, const rpca_params *const *p, rpca_state *const *st,
+                    double *const *err_hist, double *const *zeta_hist, int32_t hist_cap,
+                    void *const *ws, const size_t *ws_bytes, void *const *streams, int32_t n_streams,
+                    int32_t *status);
+
 /* Dense outputs of Algorithm 1: L_out = U diag(sigma) V^T (row stride ldl) and
  * S_out = T_zeta(D - L) (row stride lds), dtype elements, device. Either
  * pointer may be NULL. st is read only. */

@@ -12,6 +12,7 @@
 
 #include <atomic>
 #include <chrono>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -695,79 +696,253 @@ int rpca_init(const void* D, const rpca_params* p, rpca_state* st, void* ws, siz
     return RPCA_OK;
 }
 
-int rpca_solve(const void* D, const rpca_params* p, rpca_state* st, double* err_hist, double* zeta_hist,
-               int32_t hist_cap, void* ws, size_t ws_bytes, void* stream) {
-    if (!D || hist_cap < 0) return RPCA_EINVAL;
-    RPCA_TRY(check_state(st));
-    Ctx c;
-    RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
-    RPCA_TAKE_SLOT(slot, c);
-    const int P = c.L.K_init;
-    Ctrl t = base_ctrl(c, STAGE_SIGMA_D, INFINITY, 0, 1.0, 0);
-    RPCA_TRY(setup(c, t));
-    PanelArgs sa = panel_args(c);
-    sa.seed = p->seed;
-    HIP_TRY(launch_start(sa, P, c.dtype, c.s));
-    // One queue of bodies, one ahead of the host: initialisation bodies until a
-    // completed one reports the stage INIT_DONE (the body queued meanwhile is a
-    // no-op), then the entry update, the switch of the control block (both on
-    // the device) and loop bodies until the stopping rule fires. The host
-    // never waits for the stream in between.
-    // Mixed form: loop body k + 1 is enqueued once loop body k - 1 has
-    // completed, so it takes BF16 products while err_{k-1} >= mixed_err
-    // (bodies 0 and 1 always do); the first body with err below the level
-    // switches every later body to the FP32 pass. The decision reads err of a
-    // fixed body (its completion record), so it does not depend on timing.
-    // Body b has id b + 1; the host polls the records instead of queueing
-    // events, which would add a marker between the bodies.
-    const int max_bodies = 2 * t.init_max_passes + 4 + p->max_iter + 3;
-    bool in_loop = false, use_mx = c.mixed, stopped = false;
-    int loop_first = -1;   // queue index of loop body 0
-    int rc = RPCA_OK;
-    for (int b = 0; b < max_bodies && rc >= 0 && !stopped; ++b) {
-        rc = in_loop ? enqueue_body(c, D, p->r, BODY_MAIN, st->U, st->V, st->sigma, true, use_mx, b + 1)
-                     : enqueue_body(c, D, P, BODY_INIT, nullptr, nullptr, nullptr, false, false, b + 1);
-        if (rc < 0) break;
-        if (b < 1) continue;
-        BodyRecord hs;
-        rc = wait_record(c, b, &hs);
-        if (rc < 0) break;
-        hipError_t e = hipSuccess;
-        if (!in_loop) {
+// One solve (Algorithm 3, then Algorithm 1) as a queue of bodies that the host
+// advances step by step, so that several solves can share one host thread.
+// Bodies are queued one ahead of the host: initialisation bodies until a
+// completed one reports the stage INIT_DONE (the body queued meanwhile is a
+// no-op), then the entry update, the switch of the control block (both on the
+// device) and loop bodies until the stopping rule fires. Body b has id b + 1;
+// the host reads the completion record of body b - 1 (written by its last
+// kernel into mapped host memory) after queueing body b, instead of queueing
+// events, which would add a marker between the bodies.
+// Mixed form: loop body k + 1 is queued once loop body k - 1 has completed, so
+// it takes BF16 products while err_{k-1} >= mixed_err (bodies 0 and 1 always
+// do); the first body with err below the level switches every later body to
+// the FP32 pass. The decision reads err of a fixed body (its completion
+// record), so it does not depend on timing.
+class SolveJob {
+public:
+    int start(const void* D, const rpca_params* p, rpca_state* st, double* err_hist, double* zeta_hist,
+              int32_t hist_cap, void* ws, size_t ws_bytes, void* stream) {
+        if (!D || hist_cap < 0) return RPCA_EINVAL;
+        RPCA_TRY(check_state(st));
+        RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c_));
+        slot_.reset(new StatusSlot(c_.dev));
+        if (!slot_->ok()) {
+            g_last_hip_error = (int)hipErrorOutOfMemory;
+            return RPCA_EHIP;
+        }
+        c_.st_host = slot_->host();
+        c_.st_dev = slot_->dev();
+        D_ = D;
+        p_ = p;
+        st_ = st;
+        err_hist_ = err_hist;
+        zeta_hist_ = zeta_hist;
+        hist_cap_ = hist_cap;
+        P_ = c_.L.K_init;
+        const Ctrl t = base_ctrl(c_, STAGE_SIGMA_D, INFINITY, 0, 1.0, 0);
+        RPCA_TRY(setup(c_, t));
+        PanelArgs sa = panel_args(c_);
+        sa.seed = p->seed;
+        HIP_TRY(launch_start(sa, P_, c_.dtype, c_.s));
+        max_bodies_ = 2 * t.init_max_passes + 4 + p->max_iter + 3;
+        use_mx_ = c_.mixed;
+        b_ = 0;
+        return enqueue_current();
+    }
+
+    // Queues bodies while the records they depend on are there. Returns 1 once
+    // the last body is queued, 0 if the record of body b - 1 is not there yet
+    // (block = false), a negative status on failure.
+    int step(bool block) {
+        while (!queued_all_) {
+            if (b_ >= 1) {
+                BodyRecord hs;
+                if (block) {
+                    const int e = wait_record(c_, b_, &hs);
+                    if (e < 0) return fail(e);
+                } else if (!try_record(b_, &hs)) {
+                    return 0;
+                }
+                const int e = on_record(hs);
+                if (e < 0) return fail(e);
+                if (stopped_) {
+                    queued_all_ = true;
+                    break;
+                }
+            }
+            if (b_ + 1 >= max_bodies_) {
+                queued_all_ = true;
+                break;
+            }
+            ++b_;
+            const int e = enqueue_current();
+            if (e < 0) return fail(e);
+        }
+        return rc_ < 0 ? rc_ : 1;
+    }
+
+    bool queued_all() const { return queued_all_; }
+    hipStream_t stream() const { return c_.s; }
+
+    // After the last body: waits for the stream, then fills the state and the
+    // histories. Returns rpca_solve's status.
+    int finish() {
+        hipError_t e = hipStreamSynchronize(c_.s);
+        if (e != hipSuccess && rc_ >= 0) {
+            g_last_hip_error = (int)e;
+            rc_ = RPCA_EHIP;
+        }
+        RPCA_TRY(rc_);
+        Ctrl fin;
+        RPCA_TRY(read_ctrl(c_, &fin));
+        if (fin.stage != STAGE_MAIN) return RPCA_EHIP;   // unreachable: the pass cap forces convergence
+        fill_state(st_, fin);
+        st_->init_passes = fin.total_passes;
+        const int n = fin.k + 1;
+        const int cnt = n < hist_cap_ ? n : hist_cap_;
+        if (cnt > 0 && err_hist_)
+            HIP_TRY(hipMemcpyAsync(err_hist_, c_.err_hist(), sizeof(double) * cnt, hipMemcpyDeviceToHost, c_.s));
+        if (cnt > 0 && zeta_hist_)
+            HIP_TRY(hipMemcpyAsync(zeta_hist_, c_.zeta_hist(), sizeof(double) * cnt, hipMemcpyDeviceToHost, c_.s));
+        HIP_TRY(hipStreamSynchronize(c_.s));
+        return fin.stopped_by_tol ? RPCA_OK : RPCA_MAXITER;
+    }
+
+private:
+    int fail(int e) {
+        rc_ = e;
+        queued_all_ = true;
+        return e;
+    }
+
+    int enqueue_current() {
+        return in_loop_ ? enqueue_body(c_, D_, p_->r, BODY_MAIN, st_->U, st_->V, st_->sigma, true, use_mx_, b_ + 1)
+                        : enqueue_body(c_, D_, P_, BODY_INIT, nullptr, nullptr, nullptr, false, false, b_ + 1);
+    }
+
+    bool try_record(int32_t id, BodyRecord* out) const {
+        const volatile BodyRecord* r = &c_.st_host->body[id & (BODY_RING - 1)];
+        if (r->id != id) return false;
+        std::atomic_thread_fence(std::memory_order_acquire);
+        out->id = r->id;
+        out->stage = r->stage;
+        out->done = r->done;
+        out->k = r->k;
+        out->err = r->err;
+        return true;
+    }
+
+    // The record of body b - 1 (queued before body b).
+    int on_record(const BodyRecord& hs) {
+        if (!in_loop_) {
             if (hs.stage >= STAGE_INIT_DONE) {
                 prof_drop_last();   // body b ran after the stage changed: a no-op
                 // L_0: the leading r columns of the converged block; Trim and bases
-                rc = enqueue_enter(c, c.at<double>(c.L.off_Unew), c.at<double>(c.L.off_Vnew), P,
-                                   c.small()->sigma_new, st->U, st->V, st->sigma);
-                if (rc < 0) break;
-                e = launch_enter_loop(c.ctrl(), c.s);
-                if (e != hipSuccess) { g_last_hip_error = (int)e; rc = RPCA_EHIP; break; }
-                in_loop = true;
-                loop_first = b + 1;
+                RPCA_TRY(enqueue_enter(c_, c_.at<double>(c_.L.off_Unew), c_.at<double>(c_.L.off_Vnew), P_,
+                                       c_.small()->sigma_new, st_->U, st_->V, st_->sigma));
+                HIP_TRY(launch_enter_loop(c_.ctrl(), c_.s));
+                in_loop_ = true;
+                loop_first_ = b_ + 1;
             }
-        } else if (b - 1 >= loop_first) {
-            const int k_done = b - 1 - loop_first;   // loop body that has completed
-            if (use_mx && hs.err < c.mixed_err) use_mx = false;   // hs.err = err_{k_done}
+        } else if (b_ - 1 >= loop_first_) {
+            if (use_mx_ && hs.err < c_.mixed_err) use_mx_ = false;   // hs.err = err of loop body b - 1 - loop_first
             if (hs.done) {
                 prof_drop_last();   // body b was queued after the stop: a no-op
-                stopped = true;
+                stopped_ = true;
             }
         }
+        return RPCA_OK;
     }
-    hipError_t e = hipStreamSynchronize(c.s);
-    if (e != hipSuccess && rc >= 0) { g_last_hip_error = (int)e; rc = RPCA_EHIP; }
-    RPCA_TRY(rc);
-    Ctrl fin;
-    RPCA_TRY(read_ctrl(c, &fin));
-    if (fin.stage != STAGE_MAIN) return RPCA_EHIP;   // unreachable: the pass cap forces convergence
-    fill_state(st, fin);
-    st->init_passes = fin.total_passes;
-    const int n = fin.k + 1;
-    const int cnt = n < hist_cap ? n : hist_cap;
-    if (cnt > 0 && err_hist) HIP_TRY(hipMemcpyAsync(err_hist, c.err_hist(), sizeof(double) * cnt, hipMemcpyDeviceToHost, c.s));
-    if (cnt > 0 && zeta_hist) HIP_TRY(hipMemcpyAsync(zeta_hist, c.zeta_hist(), sizeof(double) * cnt, hipMemcpyDeviceToHost, c.s));
-    HIP_TRY(hipStreamSynchronize(c.s));
-    return fin.stopped_by_tol ? RPCA_OK : RPCA_MAXITER;
+
+    Ctx c_;
+    std::unique_ptr<StatusSlot> slot_;
+    const void* D_ = nullptr;
+    const rpca_params* p_ = nullptr;
+    rpca_state* st_ = nullptr;
+    double* err_hist_ = nullptr;
+    double* zeta_hist_ = nullptr;
+    int32_t hist_cap_ = 0;
+    int P_ = 0, max_bodies_ = 0, b_ = 0, loop_first_ = -1;
+    bool in_loop_ = false, use_mx_ = false, stopped_ = false, queued_all_ = false;
+    int rc_ = RPCA_OK;
+};
+
+int rpca_solve(const void* D, const rpca_params* p, rpca_state* st, double* err_hist, double* zeta_hist,
+               int32_t hist_cap, void* ws, size_t ws_bytes, void* stream) {
+    SolveJob job;
+    const int e = job.start(D, p, st, err_hist, zeta_hist, hist_cap, ws, ws_bytes, stream);
+    if (e < 0) {
+        (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));   // nothing queued stays in flight
+        return e;
+    }
+    (void)job.step(true);
+    return job.finish();
+}
+
+int rpca_solve_many(int32_t count, const void* const* D, const rpca_params* const* p, rpca_state* const* st,
+                    double* const* err_hist, double* const* zeta_hist, int32_t hist_cap, void* const* ws,
+                    const size_t* ws_bytes, void* const* streams, int32_t n_streams, int32_t* status) {
+    if (count < 0 || !status || (count > 0 && (!D || !p || !st || !ws || !ws_bytes || !streams)) ||
+        n_streams < 1 || n_streams > RPCA_MANY_MAX_STREAMS || hist_cap < 0)
+        return RPCA_EINVAL;
+    for (int32_t i = 0; i < count; ++i) {
+        status[i] = RPCA_EINVAL;
+        if (!D[i] || !p[i] || !st[i]) return RPCA_EINVAL;
+        RPCA_TRY(validate(p[i]));
+        RPCA_TRY(check_state(st[i]));
+    }
+    // Up to n_streams solves in flight, instance i on streams[i % n_streams];
+    // a new one starts once an earlier one has queued its last body and its
+    // stream has drained.
+    std::vector<std::unique_ptr<SolveJob>> live(n_streams);
+    std::vector<int32_t> who(n_streams, -1);
+    int32_t next = 0, done = 0;
+    int first_err = RPCA_OK;
+    auto t_idle = std::chrono::steady_clock::now();
+    while (done < count) {
+        bool moved = false;
+        for (int32_t k = 0; k < n_streams; ++k) {
+            if (!live[k] && next < count && next % n_streams == k) {
+                const int32_t i = next++;
+                live[k].reset(new SolveJob());
+                who[k] = i;
+                const int e = live[k]->start(D[i], p[i], st[i], err_hist ? err_hist[i] : nullptr,
+                                             zeta_hist ? zeta_hist[i] : nullptr, hist_cap, ws[i], ws_bytes[i],
+                                             streams[k]);
+                if (e < 0) {
+                    (void)hipStreamSynchronize(static_cast<hipStream_t>(streams[k]));
+                    status[i] = e;
+                    if (first_err == RPCA_OK) first_err = e;
+                    live[k].reset();
+                    ++done;
+                }
+                moved = true;
+                continue;
+            }
+            if (!live[k]) continue;
+            SolveJob& j = *live[k];
+            if (!j.queued_all()) {
+                if (j.step(false) != 0) moved = true;
+                continue;
+            }
+            const hipError_t q = hipStreamQuery(j.stream());
+            if (q == hipErrorNotReady) continue;
+            status[who[k]] = j.finish();
+            if (status[who[k]] < 0 && first_err == RPCA_OK) first_err = status[who[k]];
+            live[k].reset();
+            ++done;
+            moved = true;
+        }
+        if (moved) {
+            t_idle = std::chrono::steady_clock::now();
+            continue;
+        }
+        cpu_relax();
+        // Nothing advanced for a while: take the oldest live solve's next step
+        // blocking, which also reports a failed or drained stream.
+        if (std::chrono::steady_clock::now() - t_idle > std::chrono::microseconds(500)) {
+            for (int32_t k = 0; k < n_streams; ++k) {
+                if (live[k] && !live[k]->queued_all()) {
+                    (void)live[k]->step(true);
+                    break;
+                }
+            }
+            t_idle = std::chrono::steady_clock::now();
+        }
+    }
+    return first_err;
 }
 
 int rpca_trim(const rpca_params* p, const rpca_state* st, double* U_tilde, double* V_tilde, void* ws,

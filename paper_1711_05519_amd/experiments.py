@@ -14,6 +14,10 @@ library's solver; the comparison systems are not part of this package).
   python -m paper_1711_05519_amd.experiments errtime
       Figure 2(c): err_k against the time to reach iteration k (r = 5,
       alpha = 0.1, c = 1, n = 2500, stop at err_k < 1e-5), FP64 and FP32.
+  python -m paper_1711_05519_amd.experiments many [--count 32]
+      Throughput on many small problems (the instance pool of the learned
+      threshold: 2000 x 2000, r = 5 .. 10, alpha 0.05 .. 0.3, FP32): solves
+      one after another against rpca_solve_many on 4, 8 and 16 streams.
   python -m paper_1711_05519_amd.experiments video
       Video-shaped workload (144 x 176 pixels x 2000 frames, r = 2, the
       stand-in for the background-subtraction data): time, iterations and the
@@ -126,6 +130,36 @@ def errtime(args):
             emit(experiment="errtime", dtype=name, k=k, seconds=s, err=ik.err)
 
 
+def many(args):
+    xs = [I.config_instance(5, i, keep_L=False) for i in range(args.count)]
+    Ds = [torch.as_tensor(x.D, dtype=torch.float32, device="cuda") for x in xs]
+
+    def solvers():
+        return [R.Solver(D, x.r, x.beta, x.beta_init, x.gamma, x.mu_in, tol=x.tol, seed=1) for x, D in zip(xs, Ds)]
+
+    svs = solvers()
+    for sv in svs:          # warm-up
+        sv.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = [sv.solve().iterations for sv in svs]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    emit(experiment="many", mode="one by one", count=args.count, seconds=t_seq, per_solve=t_seq / args.count,
+         iterations=sum(its))
+    for ns in (4, 8, 16):
+        svs = solvers()
+        R.solve_many(svs, n_streams=ns)     # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = R.solve_many(svs, n_streams=ns)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        emit(experiment="many", mode=f"{ns} streams", count=args.count, seconds=t, per_solve=t / args.count,
+             iterations=sum(i.iterations for i in infos), speedup=t_seq / t,
+             same_iterations=[i.iterations for i in infos] == its)
+
+
 def video(args):
     x = I.config_instance(3, keep_L=False)
     for trim in (True, False):
@@ -137,11 +171,12 @@ def video(args):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("what", choices=["table2", "nsweep", "alphasweep", "errtime", "video", "all"])
+    ap.add_argument("what", choices=["table2", "nsweep", "alphasweep", "errtime", "video", "many", "all"])
+    ap.add_argument("--count", type=int, default=32)
     ap.add_argument("--trials", type=int, default=10)
     ap.add_argument("--reps", type=int, default=5)
     args = ap.parse_args()
-    todo = ["nsweep", "alphasweep", "errtime", "video", "table2"] if args.what == "all" else [args.what]
+    todo = ["nsweep", "alphasweep", "errtime", "video", "many", "table2"] if args.what == "all" else [args.what]
     for w in todo:
         globals()[w](args)
 

@@ -24,6 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librpca.so")
 
 RPCA_OK, RPCA_MAXITER = 0, 1
+RPCA_EINVAL, RPCA_EWORKSPACE, RPCA_EHIP, RPCA_ENODEV = -1, -2, -3, -4
 RPCA_F64, RPCA_F32 = 0, 1
 RPCA_FLAG_NO_TRIM = 1
 RPCA_FLAG_MIXED = 2
@@ -33,7 +34,7 @@ RPCA_MLP_PARAMS = 1249
 RPCA_PROF_KINDS = 3
 RPCA_MAX_RANK = 16
 
-EXPORTED = ("rpca_workspace_size", "rpca_init", "rpca_trim", "rpca_step", "rpca_solve",
+EXPORTED = ("rpca_workspace_size", "rpca_init", "rpca_trim", "rpca_step", "rpca_solve", "rpca_solve_many",
             "rpca_materialize", "rpca_tangent_products", "rpca_strerror",
             "rpca_last_hip_error", "rpca_version", "rpca_profile_enable", "rpca_profile_read",
             "rpca_relaxed_step", "rpca_mlp_forward", "rpca_mlp_backward", "rpca_mlp_adam")
@@ -90,6 +91,9 @@ def _lib():
             "rpca_trim": [P, S, vp, vp, vp, sz, vp],
             "rpca_step": [vp, P, S, vp, sz, vp],
             "rpca_solve": [vp, P, S, pd, pd, ctypes.c_int32, vp, sz, vp],
+            "rpca_solve_many": [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(P), ctypes.POINTER(S),
+                                ctypes.POINTER(pd), ctypes.POINTER(pd), ctypes.c_int32, ctypes.POINTER(vp),
+                                ctypes.POINTER(sz), ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
             "rpca_materialize": [vp, P, S, vp, ctypes.c_int64, vp, ctypes.c_int64, vp, sz, vp],
             "rpca_tangent_products": [vp, P, vp, vp, d, vp, vp, vp, vp, pd, vp, sz, vp],
             "rpca_relaxed_step": [vp, P, S, d, d, vp, vp, ctypes.c_int32, ctypes.POINTER(RelaxResult), vp, sz, vp],
@@ -216,6 +220,33 @@ def rpca_solve(D, params, state, err_hist, zeta_hist, ws, stream=None) -> int:
     cap = 0 if err_hist is None else len(err_hist)
     return _check(_lib().rpca_solve(_ptr(D), ctypes.byref(params), ctypes.byref(state), err_hist, zeta_hist,
                                     cap, w, nb, _stream(stream)), "rpca_solve")
+
+
+RPCA_MANY_MAX_STREAMS = 16
+
+
+def rpca_solve_many(Ds, params, states, err_hists, zeta_hists, wss, streams) -> list:
+    """Runs len(Ds) solves together (rpca_solve_many): instance i on
+    streams[i % len(streams)] (torch streams). err_hists / zeta_hists: lists of
+    ctypes double arrays of one length, or None. Returns the per-instance
+    statuses; raises on a negative one."""
+    n = len(Ds)
+    vp = ctypes.c_void_p
+    d_arr = (vp * n)(*[D.data_ptr() for D in Ds])
+    p_arr = (ctypes.POINTER(Params) * n)(*[ctypes.pointer(p) for p in params])
+    s_arr = (ctypes.POINTER(State) * n)(*[ctypes.pointer(s) for s in states])
+    pd = ctypes.POINTER(ctypes.c_double)
+    cap = 0 if err_hists is None else len(err_hists[0])
+    eh = (pd * n)(*[ctypes.cast(h, pd) for h in err_hists]) if err_hists is not None else None
+    zh = (pd * n)(*[ctypes.cast(h, pd) for h in zeta_hists]) if zeta_hists is not None else None
+    w_arr = (vp * n)(*[w.data_ptr() for w in wss])
+    b_arr = (ctypes.c_size_t * n)(*[w.numel() * w.element_size() for w in wss])
+    st_arr = (vp * len(streams))(*[s.cuda_stream for s in streams])
+    status = (ctypes.c_int32 * max(n, 1))()
+    rc = _lib().rpca_solve_many(n, d_arr, p_arr, s_arr, eh, zh, cap, w_arr, b_arr, st_arr, len(streams), status)
+    out = list(status[:n])
+    _check(rc, "rpca_solve_many")
+    return out
 
 
 def rpca_materialize(D, params, state, L_out, S_out, ws, stream=None) -> int:
@@ -391,6 +422,27 @@ class Solver:
         self.sigma.copy_(s)
         self.V.copy_(V)
         self.state.zeta, self.state.k, self.state.normD = float(zeta), int(k), float(normD)
+
+
+def solve_many(solvers, n_streams: int = 8) -> list:
+    """Solves the problems of several Solver objects together
+    (rpca_solve_many) on n_streams new streams; returns their SolveInfo."""
+    n_streams = max(1, min(n_streams, RPCA_MANY_MAX_STREAMS, len(solvers)))
+    dev = solvers[0].D.device if solvers else torch.device("cuda")
+    streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
+    cap = max(sv.params.max_iter for sv in solvers) + 1 if solvers else 1
+    eh = [(ctypes.c_double * cap)() for _ in solvers]
+    zh = [(ctypes.c_double * cap)() for _ in solvers]
+    torch.cuda.current_stream(dev).synchronize()   # inputs written on the current stream are complete
+    status = rpca_solve_many([sv.D for sv in solvers], [sv.params for sv in solvers], [sv.state for sv in solvers],
+                             eh, zh, [sv.ws for sv in solvers], streams)
+    out = []
+    for sv, st, e, z in zip(solvers, status, eh, zh):
+        k = sv.state.k
+        out.append(SolveInfo(status=st, iterations=k, err=sv.state.err, zeta=sv.state.zeta, err_hist=list(e[:k + 1]),
+                             zeta_hist=list(z[:k + 1]), init_passes=sv.state.init_passes,
+                             svd_sweeps=sv.state.svd_sweeps))
+    return out
 
 
 class RelaxedStep(torch.autograd.Function):

@@ -123,3 +123,12 @@ def test_mlp_entry_points_validate_before_launch(lib):
     assert lib.rpca_mlp_backward(ws, ws, None, 1, ws, None) == -1
     assert lib.rpca_mlp_adam(ws, ws, ws, ws, 0, 0.1, 0.9, 0.999, 1e-8, None) == -1
     assert lib.rpca_mlp_adam(ws, ws, ws, ws, 1, 0.1, 1.0, 0.999, 1e-8, None) == -1
+
+
+def test_solve_many_argument_checks(lib):
+    # rejected before any device work: negative count, stream counts out of range
+    f = lib.rpca_solve_many
+    st = (ctypes.c_int32 * 1)()
+    vp = (ctypes.c_void_p * 1)()
+    for count, ns in ((-1, 1), (0, 0), (0, R.RPCA_MANY_MAX_STREAMS + 1)):
+        assert f(count, None, None, None, None, None, 0, None, None, vp, ns, st) == R.RPCA_EINVAL
