@@ -1,12 +1,15 @@
 // C ABI of librpca (include/rpca.h): argument validation, workspace layout and
-// the stream-ordered orchestration of the kernels in stream.hip / panel.hip.
+// the stream-ordered orchestration of the kernels in stream.hip, stream_mx.hip,
+// panel.hip, relax.hip and mlp.hip.
 //
-// One iteration of the loop ("body") is five launches on the caller's stream:
-//   stream (one pass over D) -> gather -> complement -> update -> basis.
+// One iteration of the loop ("body") is three launches on the caller's stream
+// for FP32 D, four for FP64:
+//   stream (one pass over D) -> gather (with the 2r x 2r step for FP32)
+//   [-> complement (FP64)] -> update.
 // The host keeps one body queued ahead of the GPU and reads the stopping
-// decision, which the gather kernel publishes in mapped pinned memory, one body
-// late; bodies queued past the stop become no-ops on the device (Ctrl gating),
-// so the GPU never waits for the host and the host never blocks per iteration.
+// decision from the completion record that each body's update kernel writes
+// into mapped host memory, one body late; bodies queued past the stop become
+// no-ops on the device (Ctrl gating), so the GPU never waits for the host.
 #include <math.h>
 #include <string.h>
 

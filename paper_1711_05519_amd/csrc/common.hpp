@@ -79,7 +79,6 @@ struct Ctrl {
     int32_t init_max_passes;
     int32_t trim;        // 1: apply Algorithm 2 in the update kernel
     int32_t want_stop;   // 1: gather kernel applies the stopping rule
-    int32_t seq;
     int32_t stopped_by_tol;
     int32_t active;      // 1 while the current loop body is live (set by the gather kernel)
     int32_t jacobi_sweeps;   // sweeps of the last 2K x 2K SVD (diagnostic)

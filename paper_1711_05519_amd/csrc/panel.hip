@@ -427,7 +427,6 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
             ctrl->total_passes += 1;
         }
         ctrl->active = ctrl->done ? 0 : 1;
-        ctrl->seq += 1;
         ctrl->cnt[CNT_GATHER] = 0;
         go_on = (GRAM && a.mode == GATHER_WITH_SVD && ctrl->active) ? 1 : 0;
     }
