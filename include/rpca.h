@@ -96,7 +96,7 @@ typedef struct rpca_params {
     int32_t  max_iter;     /* iteration cap; the paper uses 100 (Section 3)                  */
     int32_t  init_block;   /* p: columns of the initial truncated-SVD iteration,
                               r <= p <= RPCA_MAX_RANK and 2p <= min(m, n);
-                              0 = default: min(r + 2, RPCA_MAX_RANK, min(m, n) / 2)        */
+                              0 = default: min(r + 1, RPCA_MAX_RANK, min(m, n) / 2)        */
     int32_t  init_max_passes; /* cap on passes over D per init stage; 0 = default (40)      */
     uint32_t flags;        /* RPCA_FLAG_*                                                    */
     uint64_t seed;         /* seeds the start block of the initial truncated SVD             */
