@@ -12,7 +12,7 @@
 //
 // Layout: workgroup of 4 waves, tile TM rows x 256 columns; each wave takes
 // blocks of 16 rows (rows i0 + 16w, i0 + 16(w + 4), ...). Phase A: the lane
-// owns columns 4l..4l+3, loads MX_BATCH rows at a time (the next batch in
+// owns columns 4l..4l+3, loads mx_batch(K) rows at a time (the next batch in
 // flight), and writes BF16 Z row-major into its wave's LDS block (row pitch
 // 260 BF16: the pad spreads the row reads over the banks). Phase B: Y1 of the
 // 16 rows, eight MFMAs over the 32-column blocks of the tile, A read from LDS
@@ -30,7 +30,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int MX_RB = 16;                 // rows per wave block (MFMA M)
 constexpr int MX_PITCH = STREAM_TN + 4;   // BF16 per LDS row
-constexpr int MX_BATCH = 4;               // rows per batch of loads in phase A
+// rows per batch of loads in phase A: 4, or 2 from K = 8 on, where the
+// registers of two batches in flight would cost a wave per SIMD
+constexpr int mx_batch(int K) { return K >= 8 ? 2 : 4; }
 
 __device__ inline void mx_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -44,14 +46,14 @@ __device__ inline uint32_t pack2(float a, float b) {
 
 __device__ inline __bf16 to_bf16(float x) { return static_cast<__bf16>(x); }
 
-// MX_BATCH rows x 4 columns of D for one lane (zeros outside the matrix).
+// NBT rows x 4 columns of D for one lane (zeros outside the matrix).
 // FULL: the tile's 256 columns are inside D and rows are 16-byte aligned, so
 // only the (wave-uniform) row bound is checked.
-template <bool FULL>
+template <int NBT, bool FULL>
 __device__ inline void mx_load_batch(const float* __restrict__ D, int64_t ldd, int i0, int i_hi, int jb, int nvalid,
-                                     float (&d)[MX_BATCH][4]) {
+                                     float (&d)[NBT][4]) {
 #pragma unroll
-    for (int b = 0; b < MX_BATCH; ++b) {
+    for (int b = 0; b < NBT; ++b) {
         const int i = i0 + b;
         const float* p = D + (size_t)i * ldd + jb;
         if constexpr (FULL) {
@@ -70,19 +72,21 @@ __device__ inline void mx_load_batch(const float* __restrict__ D, int64_t ldd, i
 }
 
 // Threshold, residual and Y2 of one batch; Z in BF16 into the wave's LDS block.
-template <int K, bool REBUILD>
-__device__ inline void mx_compute_batch(const float (&d)[MX_BATCH][4], const float* __restrict__ AL,
+// CHECK: some rows of the batch may lie past i_hi (wave-uniform choice); a
+// batch inside the tile loads its row operands without per-row conditions.
+template <int K, int NBT, bool REBUILD, bool CHECK>
+__device__ inline void mx_compute_batch(const float (&d)[NBT][4], const float* __restrict__ AL,
                                         const float* __restrict__ Uf, int i0, int i_hi, int r_local, float zeta,
                                         const float (&bl)[4][K], float (&y2)[4][K], uint16_t* zl, int lane,
                                         float& rs, float& amax) {
 #pragma unroll
-    for (int b = 0; b < MX_BATCH; ++b) {
+    for (int b = 0; b < NBT; ++b) {
         const int i = i0 + b;
         float al[K], ut[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) {
-            al[t] = (REBUILD && i < i_hi) ? AL[(size_t)i * K + t] : 0.f;
-            ut[t] = i < i_hi ? Uf[(size_t)i * K + t] : 0.f;
+            al[t] = (REBUILD && (!CHECK || i < i_hi)) ? AL[(size_t)i * K + t] : 0.f;
+            ut[t] = (!CHECK || i < i_hi) ? Uf[(size_t)i * K + t] : 0.f;
         }
         float z[4];
 #pragma unroll
@@ -117,24 +121,33 @@ __device__ inline void mx_tile(const float* __restrict__ D, const float* __restr
                                double& res, float& amax) {
     const int lr = lane & 15, lg = lane >> 4;
     const bf16x8 zero8 = {};
-    float ba[MX_BATCH][4], bb[MX_BATCH][4];
+    constexpr int NBT = mx_batch(K);
+    float ba[NBT][4], bb[NBT][4];
     int i0 = i_lo + MX_RB * wave;
-    if (i0 < i_hi) mx_load_batch<FULL>(D, g.ldd, i0, i_hi, jb, nvalid, ba);
+    if (i0 < i_hi) mx_load_batch<NBT, FULL>(D, g.ldd, i0, i_hi, jb, nvalid, ba);
     for (; i0 < i_hi; i0 += MX_RB * STREAM_WAVES) {
         float rs = 0.f;
-        // phase A: batches of MX_BATCH rows in two register buffers; the loads
+        // phase A: batches of NBT rows in two register buffers; the loads
         // of the next batch (or of the next block's first batch) are in flight
         // while one is computed. Rows at or past i_hi load as zeros.
         const int i_next = i0 + MX_RB * STREAM_WAVES;
 #pragma unroll 1
-        for (int bt = 0; bt < MX_RB / MX_BATCH; bt += 2) {
-            mx_load_batch<FULL>(D, g.ldd, i0 + MX_BATCH * (bt + 1), i_hi, jb, nvalid, bb);
-            mx_compute_batch<K, REBUILD>(ba, AL, Uf, i0 + MX_BATCH * bt, i_hi, MX_BATCH * bt, zeta, bl, y2, zl, lane,
-                                         rs, amax);
-            const int inx = (bt + 2 < MX_RB / MX_BATCH) ? i0 + MX_BATCH * (bt + 2) : i_next;
-            mx_load_batch<FULL>(D, g.ldd, inx, i_hi, jb, nvalid, ba);
-            mx_compute_batch<K, REBUILD>(bb, AL, Uf, i0 + MX_BATCH * (bt + 1), i_hi, MX_BATCH * (bt + 1), zeta, bl,
-                                         y2, zl, lane, rs, amax);
+        for (int bt = 0; bt < MX_RB / NBT; bt += 2) {
+            mx_load_batch<NBT, FULL>(D, g.ldd, i0 + NBT * (bt + 1), i_hi, jb, nvalid, bb);
+            if (i0 + NBT * (bt + 1) <= i_hi)
+                mx_compute_batch<K, NBT, REBUILD, false>(ba, AL, Uf, i0 + NBT * bt, i_hi, NBT * bt, zeta, bl, y2,
+                                                    zl, lane, rs, amax);
+            else
+                mx_compute_batch<K, NBT, REBUILD, true>(ba, AL, Uf, i0 + NBT * bt, i_hi, NBT * bt, zeta, bl, y2,
+                                                   zl, lane, rs, amax);
+            const int inx = (bt + 2 < MX_RB / NBT) ? i0 + NBT * (bt + 2) : i_next;
+            mx_load_batch<NBT, FULL>(D, g.ldd, inx, i_hi, jb, nvalid, ba);
+            if (i0 + NBT * (bt + 2) <= i_hi)
+                mx_compute_batch<K, NBT, REBUILD, false>(bb, AL, Uf, i0 + NBT * (bt + 1), i_hi, NBT * (bt + 1),
+                                                    zeta, bl, y2, zl, lane, rs, amax);
+            else
+                mx_compute_batch<K, NBT, REBUILD, true>(bb, AL, Uf, i0 + NBT * (bt + 1), i_hi, NBT * (bt + 1),
+                                                   zeta, bl, y2, zl, lane, rs, amax);
         }
         res += static_cast<double>(rs);
         mx_wave_sync();
