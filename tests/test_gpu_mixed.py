@@ -49,7 +49,8 @@ def bf16(a):
     return t.numpy()
 
 
-@pytest.mark.parametrize("m,n,r", [(300, 270, 3), (64, 520, 1), (1031, 259, 5), (200, 200, 16), (97, 1000, 7)])
+@pytest.mark.parametrize("m,n,r", [(300, 270, 3), (64, 520, 1), (1031, 259, 5), (200, 200, 16), (97, 1000, 7),
+                                   (517, 300, 10), (1000, 257, 8)])
 def test_mixed_tangent_products(m, n, r):
     say(f"mixed tangent_products m={m} n={n} r={r}")
     rng = np.random.default_rng(10 * m + n + r)
