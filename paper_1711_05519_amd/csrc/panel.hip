@@ -176,22 +176,18 @@ __device__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, con
     Small* sm = a.small;
     if (gram_form) {
         // E1 = R_U^{-1} (X1 - C* X2), E2 = R_V^{-1} X2, F1 = R_V^{-1} (Z1 - C2 Z2), F2 = R_U^{-1} Z2
-        w_mm<K, false>(cs, x2, t1);
-        w_mm<K, false>(c2, z2, t2);
+        w_mm2<K, false>(cs, x2, t1, c2, z2, t2);
         for (int e = lane; e < K * K; e += WAVE) { t1[e] = x1[e] - t1[e]; t2[e] = z1[e] - t2[e]; }
         wave_sync();
-        w_mm<K, false>(ru, t1, x1);
-        w_mm<K, false>(rv, t2, z1);
-        w_mm<K, false>(rv, x2, t1);
-        w_mm<K, false>(ru, z2, t2);
+        w_mm2<K, false>(ru, t1, x1, rv, t2, z1);
+        w_mm2<K, false>(rv, x2, t1, ru, z2, t2);
         w_store<K>(x1, sm->E1);
         w_store<K>(t1, sm->E2);
         w_store<K>(z1, sm->F1);
         w_store<K>(t2, sm->F2);
     } else {
         // E1 = R_U^{-1} X1, E2 = X2, F1 = R_V^{-1} Z1, F2 = Z2
-        w_mm<K, false>(ru, x1, t1);
-        w_mm<K, false>(rv, z1, t2);
+        w_mm2<K, false>(ru, x1, t1, rv, z1, t2);
         w_store<K>(t1, sm->E1);
         w_store<K>(x2, sm->E2);
         w_store<K>(t2, sm->F1);
@@ -297,6 +293,16 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     const int nrows = uside ? a.m : a.n;
     const int ntiles = uside ? a.n_ct : a.n_rt;
     const Acc* P = tptr<Acc>(uside ? a.P1 : a.P2);
+    const bool holder = chunk == 0 && row < nrows;
+    // the row of U_f (U side) or V_f (V side), loaded first and used last
+    T fraw[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) fraw[t] = T(0);
+    if (holder) {
+        const T* F = tptr<T>(uside ? a.Uf : a.Vf);
+#pragma unroll
+        for (int t = 0; t < K; ++t) fraw[t] = F[(size_t)row * K + t];
+    }
     // Sum over the tiles of the streaming pass. Per tile, the rows of this
     // workgroup are one contiguous block of RPB * K values ([row][t]), read as
     // 16-byte vectors: NWG groups of NV threads each take every NWG-th tile
@@ -358,17 +364,13 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
             for (int t = 0; t < K; ++t) y[t] += gsum[g * FB + slot * K + t];
     }
     __syncthreads();   // gsum is reused as sa, sb below
-    const bool holder = chunk == 0 && row < nrows;
-    double f[K];   // the row of U_f (U side) or V_f (V side)
+    double f[K];
 #pragma unroll
-    for (int t = 0; t < K; ++t) f[t] = 0.0;
+    for (int t = 0; t < K; ++t) f[t] = static_cast<double>(fraw[t]);   // zero unless holder
     if (holder) {
         double* Y = uside ? a.Y1 : a.Y2;
 #pragma unroll
         for (int t = 0; t < K; ++t) Y[(size_t)row * K + t] = y[t];
-        const T* F = tptr<T>(uside ? a.Uf : a.Vf);
-#pragma unroll
-        for (int t = 0; t < K; ++t) f[t] = static_cast<double>(F[(size_t)row * K + t]);
     } else {
 #pragma unroll
         for (int t = 0; t < K; ++t) y[t] = 0.0;
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     if (!last_block_arrives(&ctrl->cnt[CNT_GATHER], &flag)) return;
 
     // ---- last workgroup: all threads sum the partials, then one wave ----
-    __shared__ double sums[4 * K * K], ru[K * K], rv[K * K], cs[K * K], c2[K * K], tmp[K * K];
+    __shared__ double sums[4 * K * K], ru[K * K], rv[K * K], cs[K * K], c2[K * K], tmp[K * K], tmp2[K * K];
     __shared__ double g1[K * K], g2[K * K];
     __shared__ double part[GATHER_THREADS], rsum[2];
     double* craw = sums;              // U_f^T Y1
@@ -389,17 +391,24 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     double* gy2 = sums + 3 * K * K;   // Gram(Y2)
     const int gV = gridDim.x - gU;
     const bool sigma_stage = ctrl->stage == STAGE_SIGMA_D;
-    block_resid<GATHER_THREADS>(a.resid, a.n_tiles, sigma_stage, part, rsum);
+    // the residual tiles and R_U^{-1}, R_V^{-1} are loaded before the partials
+    // are summed, so that the three loads overlap
+    double rv_[RESID_LD], rw_[RESID_LD];
+    block_resid_fetch<GATHER_THREADS>(a.resid, a.n_tiles, sigma_stage, rv_, rw_);
+    double ru_pre[w_per_lane<K>()], rv_pre[w_per_lane<K>()];
+    if (threadIdx.x < WAVE) {
+        w_fetch<K>(a.small->RUinv, ru_pre);
+        w_fetch<K>(a.small->RVinv, rv_pre);
+    }
     block_sum_partials<K * K, GRAM ? 4 : 2, GATHER_THREADS>(a.gpart, gU, gV, sums, part);
+    block_resid<GATHER_THREADS>(a.resid, a.n_tiles, sigma_stage, rv_, rw_, part, rsum);
     if (threadIdx.x >= WAVE) return;
     const int lane = lane_id();
-    w_load<K>(a.small->RUinv, ru);
-    w_load<K>(a.small->RVinv, rv);
+    w_put<K>(ru_pre, ru);
+    w_put<K>(rv_pre, rv);
     // C* = R_U^{-T} (U_f^T Y1) R_V^{-1},  C2 = R_V^{-T} (V_f^T Y2) R_U^{-1}
-    w_mm<K, false>(craw, rv, tmp);
-    w_mm<K, true>(ru, tmp, cs);
-    w_mm<K, false>(craw2, ru, tmp);
-    w_mm<K, true>(rv, tmp, c2);
+    w_mm2<K, false>(craw, rv, tmp, craw2, ru, tmp2);
+    w_mm2<K, true>(ru, tmp, cs, rv, tmp2, c2);
     w_store<K>(cs, a.small->Cstar);
     w_store<K>(c2, a.small->C2);
     const double rs = rsum[0], mx = rsum[1];
@@ -434,12 +443,9 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     wave_sync();
     if (go_on) {
         // G1 = R_V^{-T} Gram(Y1) R_V^{-1} - C*^T C*,  G2 = R_U^{-T} Gram(Y2) R_U^{-1} - C2^T C2
-        w_mm<K, false>(gy1, rv, tmp);
-        w_mm<K, true>(rv, tmp, g1);
-        w_mm<K, false>(gy2, ru, tmp);
-        w_mm<K, true>(ru, tmp, g2);
-        w_mm<K, true>(cs, cs, craw);
-        w_mm<K, true>(c2, c2, craw2);
+        w_mm2<K, false>(gy1, rv, tmp, gy2, ru, tmp2);
+        w_mm2<K, true>(rv, tmp, g1, ru, tmp2, g2);
+        w_mm2<K, true>(cs, cs, craw, c2, c2, craw2);
         for (int e = lane; e < K * K; e += WAVE) { g1[e] -= craw[e]; g2[e] -= craw2[e]; }
         wave_sync();
         w_svd_tail<K>(a, ctrl, cs, c2, g1, g2, ru, rv, true);
@@ -526,34 +532,58 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
     __shared__ int flag;
     const bool main_stage = !from_m || ctrl->stage == STAGE_MAIN;
     const bool uside = (int)blockIdx.x < a.gU;
-    if (from_m) {
-        block_load_small<K>(uside ? a.small->E1 : a.small->F1, e1);
-        block_load_small<K>(uside ? a.small->E2 : a.small->F2, e2);
-    }
-    if (threadIdx.x < K)
-        sig[threadIdx.x] = from_m ? a.small->sigma_new[threadIdx.x] : (a.src_sigma ? a.src_sigma[threadIdx.x] : 1.0);
-    __syncthreads();
     const int row = (uside ? blockIdx.x : blockIdx.x - a.gU) * PANEL_THREADS + threadIdx.x;
     const int nrows = uside ? a.m : a.n;
+    T* F = tptr<T>(uside ? a.Uf : a.Vf);
+    // All loads (the row's inputs, E1, E2, sigma) are issued before any of
+    // them is used, so that their latencies overlap; raw values, converted
+    // after the barrier.
+    static_assert(K * K <= PANEL_THREADS, "one entry of E1, E2 per thread");
+    const int tid = threadIdx.x;
+    T fin[K];
+    double in2[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) { fin[t] = T(0); in2[t] = 0.0; }
+    if (row < nrows) {
+        if (from_m) {
+            const double* S2 = uside ? a.S2U : a.S2V;
+#pragma unroll
+            for (int t = 0; t < K; ++t) { fin[t] = F[(size_t)row * K + t]; in2[t] = S2[(size_t)row * K + t]; }
+        } else {
+            const double* src = uside ? a.srcU : a.srcV;
+#pragma unroll
+            for (int t = 0; t < K; ++t) in2[t] = src[(size_t)row * a.ld_src + t];
+        }
+    }
+    double e1v = 0.0, e2v = 0.0, sgv = 1.0;
+    if (from_m && tid < K * K) {
+        const int at = (tid / K) * KMAX + tid % K;
+        e1v = (uside ? a.small->E1 : a.small->F1)[at];
+        e2v = (uside ? a.small->E2 : a.small->F2)[at];
+    }
+    if (tid < K) {
+        if (from_m) sgv = a.small->sigma_new[tid];
+        else if (a.src_sigma) sgv = a.src_sigma[tid];
+    }
+    if (tid < K * K) { e1[tid] = e1v; e2[tid] = e2v; }
+    if (tid < K) sig[tid] = sgv;
+    __syncthreads();
     double gv[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) gv[t] = 0.0;
     if (row < nrows) {
-        T* F = tptr<T>(uside ? a.Uf : a.Vf);
         double un[K];
         if (from_m) {
-            const double* S2 = uside ? a.S2U : a.S2V;
-            double f[K], s2[K], p1[K], p2[K];
+            double in1[K], p1[K], p2[K];
 #pragma unroll
-            for (int t = 0; t < K; ++t) { f[t] = static_cast<double>(F[(size_t)row * K + t]); s2[t] = S2[(size_t)row * K + t]; }
-            rowmul<K>(f, e1, p1);
-            rowmul<K>(s2, e2, p2);
+            for (int t = 0; t < K; ++t) in1[t] = static_cast<double>(fin[t]);
+            rowmul<K>(in1, e1, p1);   // U_f E1
+            rowmul<K>(in2, e2, p2);   // S_U E2
 #pragma unroll
             for (int t = 0; t < K; ++t) un[t] = p1[t] + p2[t];
         } else {
-            const double* src = uside ? a.srcU : a.srcV;
 #pragma unroll
-            for (int t = 0; t < K; ++t) un[t] = src[(size_t)row * a.ld_src + t];
+            for (int t = 0; t < K; ++t) un[t] = in2[t];
         }
         double* dst = uside ? a.Unew : a.Vnew;
         if (dst) {

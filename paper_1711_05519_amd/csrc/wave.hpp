@@ -41,6 +41,26 @@ __device__ inline void w_store(const double* s, double* __restrict__ g) {
     for (int e = lane_id(); e < K * K; e += WAVE) g[(e / K) * KMAX + (e % K)] = s[e];
     wave_sync();
 }
+// Global -> registers -> LDS in two steps, so that the load can be issued
+// early and its latency overlap other work: lane l holds entries l, l + WAVE, ...
+template <int K> constexpr int w_per_lane() { return (K * K + WAVE - 1) / WAVE; }
+template <int K>
+__device__ inline void w_fetch(const double* __restrict__ g, double (&v)[w_per_lane<K>()]) {
+#pragma unroll
+    for (int u = 0; u < w_per_lane<K>(); ++u) {
+        const int e = lane_id() + u * WAVE;
+        v[u] = e < K * K ? g[(e / K) * KMAX + (e % K)] : 0.0;
+    }
+}
+template <int K>
+__device__ inline void w_put(const double (&v)[w_per_lane<K>()], double* s) {
+#pragma unroll
+    for (int u = 0; u < w_per_lane<K>(); ++u) {
+        const int e = lane_id() + u * WAVE;
+        if (e < K * K) s[e] = v[u];
+    }
+    wave_sync();
+}
 // C = op(A) B (K x K, ld K, LDS); op = transpose when TA
 template <int K, bool TA>
 __device__ inline void w_mm(const double* A, const double* B, double* C) {
@@ -49,6 +69,22 @@ __device__ inline void w_mm(const double* A, const double* B, double* C) {
         double acc = 0.0;
         for (int l = 0; l < K; ++l) acc = fma(TA ? A[l * K + i] : A[i * K + l], B[l * K + j], acc);
         C[e] = acc;
+    }
+    wave_sync();
+}
+// Two independent products C = op(A) B and F = op(D) E in one pass
+template <int K, bool TA>
+__device__ inline void w_mm2(const double* A, const double* B, double* C, const double* D, const double* E,
+                             double* F) {
+    for (int x = lane_id(); x < 2 * K * K; x += WAVE) {
+        const bool second = x >= K * K;
+        const int e = second ? x - K * K : x;
+        const double* P = second ? D : A;
+        const double* Q = second ? E : B;
+        const int i = e / K, j = e % K;
+        double acc = 0.0;
+        for (int l = 0; l < K; ++l) acc = fma(TA ? P[l * K + i] : P[i * K + l], Q[l * K + j], acc);
+        (second ? F : C)[e] = acc;
     }
     wave_sync();
 }
@@ -99,36 +135,63 @@ __device__ void block_sum_partials(const double* __restrict__ gpart, int gU, int
     }
 }
 
+template <int CTRL> __device__ inline double dpp64(double x);
+__device__ inline double row16_sum(double x);
+__device__ inline double row16_max(double x);
+__device__ inline double readlane64(double x, int l);
+
 // Sum of the per-tile residuals (and, if want_max, the max of the per-tile
 // max |D_ij| stored after them) by the whole workgroup, in a fixed order.
-// out[0] = sum, out[1] = max. part: at least 2 * NT / WAVE doubles of LDS.
+// out[0] = sum, out[1] = max. part: at least 2 * NT / 16 doubles of LDS.
+// Split in two: block_resid_fetch issues the loads of the first RESID_LD * NT
+// tiles into registers (so that other loads can follow before they are
+// used), block_resid adds them, and any further tiles, in tile order per thread.
+constexpr int RESID_LD = 2;
 template <int NT>
-__device__ void block_resid(const double* __restrict__ resid, int n_tiles, bool want_max, double* part,
-                            double* out) {
+__device__ inline void block_resid_fetch(const double* __restrict__ resid, int n_tiles, bool want_max,
+                                         double (&v)[RESID_LD], double (&w)[RESID_LD]) {
+#pragma unroll
+    for (int u = 0; u < RESID_LD; ++u) {
+        const int b = threadIdx.x + u * NT;
+        v[u] = b < n_tiles ? resid[b] : 0.0;
+        w[u] = (want_max && b < n_tiles) ? resid[n_tiles + b] : 0.0;
+    }
+}
+template <int NT>
+__device__ void block_resid(const double* __restrict__ resid, int n_tiles, bool want_max,
+                            const double (&v)[RESID_LD], const double (&w)[RESID_LD], double* part, double* out) {
     const int t = threadIdx.x;
     double sm = 0.0, mx = 0.0;
-    for (int b = t; b < n_tiles; b += NT) {
+#pragma unroll
+    for (int u = 0; u < RESID_LD; ++u) {
+        sm += v[u];
+        mx = fmax(mx, w[u]);
+    }
+    for (int b = t + RESID_LD * NT; b < n_tiles; b += NT) {
         sm += resid[b];
         if (want_max) mx = fmax(mx, resid[n_tiles + b]);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        sm += __shfl_xor(sm, off, WAVE);
-        mx = fmax(mx, __shfl_xor(mx, off, WAVE));
-    }
-    constexpr int NW = NT / WAVE;
-    if ((t & (WAVE - 1)) == 0) {
-        part[t / WAVE] = sm;
-        part[NW + t / WAVE] = mx;
+    // sums and maxima over each row of 16 lanes by DPP; the four rows of a
+    // wave go to LDS separately
+    sm = row16_sum(sm);
+    mx = row16_max(mx);
+    constexpr int NW = NT / 16;
+    static_assert(NW <= WAVE, "one row sum per lane of the first wave");
+    if ((t & 15) == 0) {
+        part[t / 16] = sm;
+        part[NW + t / 16] = mx;
     }
     __syncthreads();
-    if (t == 0) {
-        double a = 0.0, m = 0.0;
-        for (int w = 0; w < NW; ++w) {
-            a += part[w];
-            m = fmax(m, part[NW + w]);
+    if (t < WAVE) {
+        double a = t < NW ? part[t] : 0.0, m = t < NW ? part[NW + t] : 0.0;
+        a = row16_sum(a);
+        m = row16_max(m);
+        a = (readlane64(a, 0) + readlane64(a, 16)) + (readlane64(a, 32) + readlane64(a, 48));
+        m = fmax(fmax(readlane64(m, 0), readlane64(m, 16)), fmax(readlane64(m, 32), readlane64(m, 48)));
+        if (t == 0) {
+            out[0] = a;
+            out[1] = m;
         }
-        out[0] = a;
-        out[1] = m;
     }
     __syncthreads();
 }
@@ -163,8 +226,8 @@ __device__ void w_chol_inv2(const double* G0, double* R0, double* Ri0, const dou
         const double d = h ? readlane64(g[j], 32 + j) : readlane64(g[j], j);
         const double gjj = G[j * K + j];
         const bool live = gjj > 1e-300 && d > CHOL_DEAD_REL * gjj;
-        const double rjj = live ? sqrt(d) : 0.0;
-        const double ivj = live ? 1.0 / rjj : 0.0;
+        const double ivj = live ? rsqrt(d) : 0.0;   // one reciprocal square root, no division
+        const double rjj = live ? d * ivj : 0.0;
         inv[j] = ivj;
         r[j] = (c == j) ? rjj : (c > j ? g[j] * ivj : 0.0);   // R[j][c]
 #pragma unroll
@@ -200,6 +263,20 @@ template <int CTRL> __device__ inline double dpp64(double x) {
     const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
     return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ inline double row16_sum(double x) {
+    x += dpp64<0xB1>(x);
+    x += dpp64<0x4E>(x);
+    x += dpp64<0x141>(x);
+    x += dpp64<0x128>(x);
+    return x;
+}
+__device__ inline double row16_max(double x) {
+    x = fmax(x, dpp64<0xB1>(x));
+    x = fmax(x, dpp64<0x4E>(x));
+    x = fmax(x, dpp64<0x141>(x));
+    x = fmax(x, dpp64<0x128>(x));
+    return x;
 }
 // Sum over aligned groups of LP lanes (LP = 1, 2, 4, 8, 16), result in every lane.
 template <int LP> __device__ inline double group_sum(double x) {
