@@ -64,7 +64,7 @@ __device__ inline void block_load_small(const double* __restrict__ g, double* s)
 // fixed-order DPP reduction over the group (bitwise reproducible). sa, sb: LDS
 // scratch of NR*K doubles each; every thread of the block must call it.
 template <int K, int NR, int NT>
-__device__ void rows_outer_sum(const double (&a)[K], const double (&b)[K], bool writer, int slot, double* sa,
+__device__ __forceinline__ void rows_outer_sum(const double (&a)[K], const double (&b)[K], bool writer, int slot, double* sa,
                                double* sb, double* __restrict__ dst) {
     constexpr int G0 = pow2_floor(NT / (K * K) > 0 ? NT / (K * K) : 1);
     constexpr int G = G0 > 16 ? 16 : G0;
@@ -96,7 +96,7 @@ constexpr double MLP_O_CLIP = 5.0;   // the correction exp(o) stays within e^-5 
 // Output o of the threshold network (parameters th, FP32, layout of the
 // training kernels) at features phi, evaluated in FP64 by one wave: lane j < 32
 // owns hidden unit j. The result is valid in every lane.
-__device__ inline double w_mlp(const float* __restrict__ th, const double (&phi)[MLP_IN]) {
+__device__ __forceinline__ double w_mlp(const float* __restrict__ th, const double (&phi)[MLP_IN]) {
     constexpr int OB1 = MLP_H * MLP_IN, OW2 = OB1 + MLP_H, OB2 = OW2 + MLP_H * MLP_H, OW3 = OB2 + MLP_H,
                   OB3 = OW3 + MLP_H;
     __shared__ double h1s[MLP_H];
@@ -127,7 +127,7 @@ __device__ inline double w_mlp(const float* __restrict__ th, const double (&phi)
 //   U_{k+1} = U_f E1 + S_U E2,   V_{k+1} = V_f F1 + S_V F2,
 // with (S_U, S_V) = (Y1, Y2) when gram_form, (W1, W2) otherwise.
 template <int K>
-__device__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, const double* c2,
+__device__ __forceinline__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, const double* c2,
                            const double* g1, const double* g2, const double* ru, const double* rv,
                            bool gram_form) {
     constexpr int N = 2 * K;

@@ -100,7 +100,7 @@ __device__ inline void w_mm2(const double* A, const double* B, double* C, const 
 // round over up to 16 S partials costs one memory latency. part: NT doubles
 // of LDS.
 template <int E, int J, int NT>
-__device__ void block_sum_partials(const double* __restrict__ gpart, int gU, int gV, double* out, double* part) {
+__device__ __forceinline__ void block_sum_partials(const double* __restrict__ gpart, int gU, int gV, double* out, double* part) {
     constexpr int PAIRS = J * E;
     constexpr int PR = PAIRS >= NT ? NT : PAIRS;   // pairs per round
     constexpr int S = NT / PR;                     // splits per pair
@@ -158,7 +158,7 @@ __device__ inline void block_resid_fetch(const double* __restrict__ resid, int n
     }
 }
 template <int NT>
-__device__ void block_resid(const double* __restrict__ resid, int n_tiles, bool want_max,
+__device__ __forceinline__ void block_resid(const double* __restrict__ resid, int n_tiles, bool want_max,
                             const double (&v)[RESID_LD], const double (&w)[RESID_LD], double* part, double* out) {
     const int t = threadIdx.x;
     double sm = 0.0, mx = 0.0;
@@ -212,7 +212,7 @@ __device__ inline double readlane64(double x, int l) {
 // marks a numerically dependent column: its row of R and column of R^{-1}
 // are 0. R^{-1} by back substitution from R in LDS, column c in lane c.
 template <int K>
-__device__ void w_chol_inv2(const double* G0, double* R0, double* Ri0, const double* G1, double* R1,
+__device__ __forceinline__ void w_chol_inv2(const double* G0, double* R0, double* Ri0, const double* G1, double* R1,
                             double* Ri1) {
     static_assert(K <= 32, "one column per lane of a half wave");
     const int lane = lane_id();
@@ -302,7 +302,7 @@ constexpr int pow2_floor(int x) { int p = 1; while (p * 2 <= x) p *= 2; return p
 // sig[] is descending and Uo/Vo hold the left/right singular vectors as
 // columns (column-major). Returns the sweep count.
 template <int N, bool QUAD_STOP = true>
-__device__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, double* Vo, double neg2 = 0.0) {
+__device__ __forceinline__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, double* Vo, double neg2 = 0.0) {
     static_assert(N % 2 == 0 && N <= 2 * KMAX, "even N up to 2*KMAX");
     constexpr int NP = N / 2;
     constexpr int LP0 = pow2_floor(WAVE / NP);
