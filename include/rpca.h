@@ -57,15 +57,19 @@ extern "C" {
 
 /* ---- flags ------------------------------------------------------------- */
 #define RPCA_FLAG_NO_TRIM 1u  /* AccAltProj without trim (Section 3): U~ = U_k, V~ = V_k */
-/* Mixed-precision form (RPCA_F32 only): the tangent product
- * Y1 = (D - S_k) V~ of a loop body runs on the matrix cores with BF16 operands
- * and FP32 accumulation; Y2 = (D - S_k)^T U~, the rebuild of L_k, the
- * threshold, the residual and err_k stay FP32, as does all small algebra
- * (FP64). In rpca_solve, body k (which computes err_k and L_{k+1}) takes BF16
- * products while err_j >= mixed_err for every j <= k - 2 (bodies 0 and 1
- * always do: the host decides one body ahead); every later body is the FP32
- * one. rpca_step takes BF16 products while the state's err >= mixed_err (or
- * is unknown). Not part of the paper: a precision choice of this library. */
+/* Mixed-precision form (RPCA_F32 only): of the tangent product
+ * Y1 = (D - S_k) V~ = L_k V~ + E V~ (E = D - L_k - S_k, the residual part), the
+ * product E V~ of a loop body runs on the matrix cores with BF16 operands and
+ * FP32 accumulation, and L_k V~ is added exactly from the factors; so the
+ * BF16 rounding error of Y1 is about 2^-8 err_k relative and falls with err_k.
+ * Y2 = (D - S_k)^T U~, the rebuild of L_k, the threshold, the residual and
+ * err_k stay FP32, as does all small algebra (FP64). By default every loop
+ * body takes BF16 products. With mixed_err > 0, body k of rpca_solve (which
+ * computes err_k and L_{k+1}) takes them while err_j >= mixed_err for every
+ * j <= k - 2 (bodies 0 and 1 always do: the host decides one body ahead) and
+ * every later body is the FP32 one; rpca_step takes them while the state's
+ * err >= mixed_err (or is unknown). Not part of the paper: a precision choice
+ * of this library. */
 #define RPCA_FLAG_MIXED 2u
 /* Workspace for rpca_relaxed_step (threshold training; r <= 10). */
 #define RPCA_FLAG_TRAINING 4u
@@ -101,7 +105,7 @@ typedef struct rpca_params {
     uint32_t flags;        /* RPCA_FLAG_*                                                    */
     uint64_t seed;         /* seeds the start block of the initial truncated SVD             */
     double   mixed_err;    /* with RPCA_FLAG_MIXED: BF16-product bodies while err_k >= this;
-                              <= 0 selects the default 1e-3                                  */
+                              <= 0: BF16 products in every loop body (default)              */
     const float *zeta_mlp; /* with RPCA_FLAG_LEARNED: device parameters of the network      */
 } rpca_params;
 

@@ -30,7 +30,9 @@ namespace {
 thread_local int g_last_hip_error = 0;
 
 constexpr int DEFAULT_INIT_MAX_PASSES = 40;
-constexpr double DEFAULT_MIXED_ERR = 1e-3;
+// BF16-product bodies while err_k >= mixed_err; the default 0 keeps them to
+// the end (their rounding error scales with err_k)
+constexpr double DEFAULT_MIXED_ERR = 0.0;
 constexpr int MAX_DEVICES = 64;
 
 #define HIP_TRY(expr)                                    \
@@ -480,6 +482,7 @@ int enqueue_body(const Ctx& c, const void* D, int K, int body, double* state_U, 
     RPCA_TRY(stream_launch(sa, K, c.dtype, rebuild, mx, c.s));
     PanelArgs pa = panel_args(c, g);
     pa.body = body;
+    pa.lcorr = rebuild ? 1 : 0;
     if (with_hist) {
         pa.err_hist = c.err_hist();
         pa.zeta_hist = c.zeta_hist();
@@ -616,7 +619,9 @@ int threshold_pass(const Ctx& c, const void* D, bool rebuild) {
     const int K = c.p->r;
     const Geo g = geo_for(c, K, rebuild);
     RPCA_TRY(stream_launch(stream_args(c, D, BODY_ANY, g), K, c.dtype, rebuild, false, c.s));
-    HIP_TRY(launch_gather(panel_args(c, g), K, c.dtype, c.s));
+    PanelArgs pa = panel_args(c, g);
+    pa.lcorr = rebuild ? 1 : 0;
+    HIP_TRY(launch_gather(pa, K, c.dtype, c.s));
     return RPCA_OK;
 }
 
@@ -1149,11 +1154,13 @@ int rpca_tangent_products(const void* D, const rpca_params* p, const double* A_L
     HIP_TRY(launch_convert(B_L, c.ws + c.L.off_BL, p->n * K, nullptr, K, c.dtype, c.s));
     HIP_TRY(launch_convert(U_t, c.ws + c.L.off_Uf, p->m * K, nullptr, K, c.dtype, c.s));
     HIP_TRY(launch_convert(V_t, c.ws + c.L.off_Vf, p->n * K, nullptr, K, c.dtype, c.s));
+    HIP_TRY(launch_cross(panel_args(c), K, c.dtype, c.s));   // AL^T U_f, BL^T V_f for the gather
     const Geo g = geo_for(c, K, true, c.mixed);
     RPCA_TRY(stream_launch(stream_args(c, D, BODY_ANY, g), K, c.dtype, true, c.mixed, c.s));
     PanelArgs pa = panel_args(c, g);
     pa.Y1 = Y1;
     pa.Y2 = Y2;
+    pa.lcorr = 1;
     HIP_TRY(launch_gather(pa, K, c.dtype, c.s));
     Ctrl t;
     RPCA_TRY(read_ctrl(c, &t));

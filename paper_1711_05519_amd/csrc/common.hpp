@@ -45,7 +45,7 @@ enum Body : int {
 
 // Counter slots for the last-workgroup-finishes pattern.
 enum CounterSlot : int {
-    CNT_GATHER = 0, CNT_COMPLEMENT = 1, CNT_UPDATE = 2, CNT_BASIS = 3, CNT_START = 4, CNT_RELAX = 5,
+    CNT_GATHER = 0, CNT_COMPLEMENT = 1, CNT_UPDATE = 2, CNT_BASIS = 3, CNT_START = 4, CNT_RELAX = 5, CNT_CROSS = 6,
     CNT_COUNT = 8,
 };
 
@@ -114,6 +114,12 @@ struct Small {
     double RBinv[KMAX * KMAX];
     double sigma_new[KMAX];
     double sigma_M[2 * KMAX];
+    // Cross products of the rebuild factors with the bases of a streaming
+    // pass: GAU = AL^T U_f, GBV = BL^T V_f (products of the stored values).
+    // With Z = D - S = L + E, E = D - L - S, the pass forms E V_f and E^T U_f
+    // and the gather adds L V_f = AL GBV and L^T U_f = BL GAU.
+    double GAU[KMAX * KMAX];
+    double GBV[KMAX * KMAX];
 };
 
 __host__ __device__ constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }

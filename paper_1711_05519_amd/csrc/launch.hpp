@@ -78,6 +78,7 @@ struct PanelArgs {
     int32_t mode;             // kernel-specific
     int32_t body;             // Body of the gather kernel
     int32_t gated;            // basis kernel: skip when the body is not active
+    int32_t lcorr;            // gather: the pass rebuilt L; add AL GBV to Y1 and BL GAU to Y2
 };
 
 // Results of one relaxed iteration (device, written by its tail kernel).
@@ -120,6 +121,7 @@ hipError_t launch_materialize(const MaterializeArgs& a, int K, int dtype, hipStr
 hipError_t launch_gather(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_complement(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_update(const PanelArgs& a, int K, int dtype, hipStream_t s);
+hipError_t launch_cross(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_basis(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_start(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, hipStream_t s);

@@ -294,14 +294,20 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     const int ntiles = uside ? a.n_ct : a.n_rt;
     const Acc* P = tptr<Acc>(uside ? a.P1 : a.P2);
     const bool holder = chunk == 0 && row < nrows;
-    // the row of U_f (U side) or V_f (V side), loaded first and used last
-    T fraw[K];
+    // the row of U_f (U side) or V_f (V side), and (rebuilding pass) of AL or
+    // BL, loaded first and used last
+    T fraw[K], lraw[K];
 #pragma unroll
-    for (int t = 0; t < K; ++t) fraw[t] = T(0);
+    for (int t = 0; t < K; ++t) fraw[t] = lraw[t] = T(0);
     if (holder) {
         const T* F = tptr<T>(uside ? a.Uf : a.Vf);
 #pragma unroll
         for (int t = 0; t < K; ++t) fraw[t] = F[(size_t)row * K + t];
+        if (a.lcorr) {
+            const T* LF = tptr<T>(uside ? a.AL : a.BL);
+#pragma unroll
+            for (int t = 0; t < K; ++t) lraw[t] = LF[(size_t)row * K + t];
+        }
     }
     // Sum over the tiles of the streaming pass. Per tile, the rows of this
     // workgroup are one contiguous block of RPB * K values ([row][t]), read as
@@ -364,6 +370,17 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
             for (int t = 0; t < K; ++t) y[t] += gsum[g * FB + slot * K + t];
     }
     __syncthreads();   // gsum is reused as sa, sb below
+    if (holder && a.lcorr) {
+        // Y1 = E V_f + AL (BL^T V_f),  Y2 = E^T U_f + BL (AL^T U_f)
+        const double* G = uside ? a.small->GBV : a.small->GAU;
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            double c = 0.0;
+#pragma unroll
+            for (int u = 0; u < K; ++u) c = fma(static_cast<double>(lraw[u]), G[u * KMAX + t], c);
+            y[t] += c;
+        }
+    }
     double f[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) f[t] = static_cast<double>(fraw[t]);   // zero unless holder
@@ -568,9 +585,9 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
     if (tid < K * K) { e1[tid] = e1v; e2[tid] = e2v; }
     if (tid < K) sig[tid] = sgv;
     __syncthreads();
-    double gv[K];
+    double gv[K], lf[K];   // the new basis row and the stored rebuild-factor row (zero past the end)
 #pragma unroll
-    for (int t = 0; t < K; ++t) gv[t] = 0.0;
+    for (int t = 0; t < K; ++t) gv[t] = lf[t] = 0.0;
     if (row < nrows) {
         double un[K];
         if (from_m) {
@@ -594,7 +611,11 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
             // rebuild factors of L: AL = U diag(sigma), BL = V
             T* LF = tptr<T>(uside ? a.AL : a.BL);
 #pragma unroll
-            for (int t = 0; t < K; ++t) LF[(size_t)row * K + t] = static_cast<T>(uside ? un[t] * sig[t] : un[t]);
+            for (int t = 0; t < K; ++t) {
+                const T v = static_cast<T>(uside ? un[t] * sig[t] : un[t]);
+                LF[(size_t)row * K + t] = v;
+                lf[t] = static_cast<double>(v);
+            }
         }
         // Algorithm 2: scale the row by min{1, c / ||row||}; c = sqrt(mu r / m) for U, sqrt(mu r / n) for V.
         double wgt = 1.0;
@@ -619,14 +640,23 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
             }
         }
     }
-    rows_outer_sum<K, PANEL_THREADS, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
+    double* gp = a.gpart + (size_t)blockIdx.x * GPART_STRIDE;
+    rows_outer_sum<K, PANEL_THREADS, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, gp);
+    // AL^T U_f and BL^T V_f for the gather of the next pass (main stage: the
+    // next pass rebuilds L)
+    if (main_stage) rows_outer_sum<K, PANEL_THREADS, PANEL_THREADS>(lf, gv, true, threadIdx.x, sa, sb, gp + KMAX * KMAX);
     if (!last_block_arrives(&ctrl->cnt[CNT_UPDATE], &flag)) return;
-    __shared__ double gg[2 * K * K], rr[K * K], ri[K * K], rr2[K * K], ri2[K * K], part[PANEL_THREADS];
+    __shared__ double gg[4 * K * K], rr[K * K], ri[K * K], rr2[K * K], ri2[K * K], part[PANEL_THREADS];
     double* g = gg;
     double* gb = gg + K * K;
-    block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, a.gU, a.gV, gg, part);
+    if (main_stage) block_sum_partials<K * K, 4, PANEL_THREADS>(a.gpart, a.gU, a.gV, gg, part);
+    else block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, a.gU, a.gV, gg, part);
     if (threadIdx.x >= WAVE) return;
     const bool exact = a.mode == UPDATE_ENTER_EXACT;
+    if (main_stage) {
+        w_store<K>(gg + 2 * K * K, a.small->GAU);
+        w_store<K>(gg + 3 * K * K, a.small->GBV);
+    }
     w_chol_inv2<K>(g, rr, ri, gb, rr2, ri2);
     w_store<K>(ri, exact ? a.small->RAinv : a.small->RUinv);
     w_store<K>(ri2, exact ? a.small->RBinv : a.small->RVinv);
@@ -636,6 +666,40 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
         if (!from_m && ctrl->stage == STAGE_INIT_DONE) ctrl->stage = STAGE_MAIN;
         ctrl->cnt[CNT_UPDATE] = 0;
     }
+}
+
+// ---- cross products AL^T U_f, BL^T V_f of given factors and bases -----------
+// For a rebuilding pass whose factors and bases were written elsewhere than by
+// the update kernel (which forms the same products itself).
+template <typename T, int K>
+__global__ __launch_bounds__(PANEL_THREADS) void k_cross(PanelArgs a) {
+    Ctrl* ctrl = a.ctrl;
+    __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K];
+    __shared__ int flag;
+    const bool uside = (int)blockIdx.x < a.gU;
+    const int row = (uside ? blockIdx.x : blockIdx.x - a.gU) * PANEL_THREADS + threadIdx.x;
+    const int nrows = uside ? a.m : a.n;
+    double lf[K], f[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) lf[t] = f[t] = 0.0;
+    if (row < nrows) {
+        const T* LF = tptr<T>(uside ? a.AL : a.BL);
+        const T* F = tptr<T>(uside ? a.Uf : a.Vf);
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            lf[t] = static_cast<double>(LF[(size_t)row * K + t]);
+            f[t] = static_cast<double>(F[(size_t)row * K + t]);
+        }
+    }
+    rows_outer_sum<K, PANEL_THREADS, PANEL_THREADS>(lf, f, true, threadIdx.x, sa, sb,
+                                                    a.gpart + (size_t)blockIdx.x * GPART_STRIDE);
+    if (!last_block_arrives(&ctrl->cnt[CNT_CROSS], &flag)) return;
+    __shared__ double gg[2 * K * K], part[PANEL_THREADS];
+    block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, a.gU, a.gV, gg, part);
+    if (threadIdx.x >= WAVE) return;
+    w_store<K>(gg, a.small->GAU);
+    w_store<K>(gg + K * K, a.small->GBV);
+    if (lane_id() == 0) ctrl->cnt[CNT_CROSS] = 0;
 }
 
 // ---- FP64 orthonormal bases U~ = A R_A^{-1} of the trimmed factors ------------
@@ -761,6 +825,9 @@ RPCA_PANEL_LAUNCHER(launch_complement, (unsigned)(a.gU + a.gV), PANEL_THREADS)
 #undef KFUN
 #define KFUN k_update
 RPCA_PANEL_LAUNCHER(launch_update, (unsigned)(a.gU + a.gV), PANEL_THREADS)
+#undef KFUN
+#define KFUN k_cross
+RPCA_PANEL_LAUNCHER(launch_cross, (unsigned)(a.gU + a.gV), PANEL_THREADS)
 #undef KFUN
 #define KFUN k_basis
 RPCA_PANEL_LAUNCHER(launch_basis, (unsigned)(a.gU + a.gV), PANEL_THREADS)

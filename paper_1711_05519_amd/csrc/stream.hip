@@ -1,18 +1,22 @@
 // The streaming pass over D: the only kernels of an iteration that touch the
 // m x n data. One read of D computes, for the current iterate L = AL BL^T and
 // threshold zeta (Section 2.1 and Algorithm 1):
-//   x = D - L,  S = T_zeta(x)  (never stored),  Z = D - S,
-//   resid = sum over |x| <= zeta of x^2          (numerator of err^2, Section 3)
-//   Y1 = Z Vf,  Y2 = Z^T Uf                      (the two n x n by n x r products
-//                                                  of the fast H_r(P_T(.)) update)
-// so that the threshold of iteration k and the tangent products of iteration
-// k+1 share one pass. L is rebuilt tile by tile in registers and never written.
+//   x = D - L,  S = T_zeta(x)  (never stored),  E = D - L - S  (x where |x| <= zeta),
+//   resid = sum of E_ij^2                        (numerator of err^2, Section 3)
+//   E Vf,  E^T Uf
+// The tangent products of the fast H_r(P_T(.)) update are Y1 = Z Vf and
+// Y2 = Z^T Uf with Z = D - S = L + E; their rank-K part L Vf = AL (BL^T Vf) and
+// L^T Uf = BL (AL^T Uf) is added by the gather from the factors (exactly, in
+// FP64), so the pass accumulates only E, whose size is that of the residual:
+// the rounding of the accumulation scales with err_k instead of with |D|. The
+// threshold of iteration k and the products of iteration k+1 share one pass;
+// L is rebuilt tile by tile in registers and never written.
 //
 // Layout: a workgroup of 4 waves owns a tile of TM rows x 256 columns. Each lane
 // owns 4 consecutive columns (one 16-byte load per row for FP32) and keeps the
 // matching rows of BL and Vf in registers; the 4 waves walk interleaved rows.
-// Row data (AL, Uf) are wave-uniform and come through scalar loads. Y2 then
-// accumulates per lane with no communication; the per-row sums of Y1 are
+// Row data (AL, Uf) are wave-uniform and come through scalar loads. E^T Uf then
+// accumulates per lane with no communication; the per-row sums of E Vf are
 // reduced across the 64 lanes in batches with a reduce-scatter built from
 // v_permlane32_swap, v_permlane16_swap and DPP moves, which leaves one finished
 // sum per lane. Tile partials go to P1/P2 and are summed in FP64 by the gather
@@ -217,13 +221,12 @@ __device__ __forceinline__ void compute_batch(
                 }
                 if constexpr (!REBUILD) amax = fmax(amax, fabs(x));   // L = 0: x = D_ij
                 const bool big = fabs(x) > zeta;   // S_ij = x  (T_zeta keeps |x| > zeta)
-                const T e = big ? T(0) : x;        // entry of D - L - S
+                const T e = big ? T(0) : x;        // entry of E = D - L - S
                 rs = fma(e, e, rs);
-                const T z = big ? dv - x : dv;     // Z = D - S
 #pragma unroll
                 for (int t = 0; t < K; ++t) {
-                    y2[s][t] = fma(z, ut[t], y2[s][t]);
-                    p[b * K + t] = fma(z, vt[s][t], p[b * K + t]);
+                    y2[s][t] = fma(e, ut[t], y2[s][t]);
+                    p[b * K + t] = fma(e, vt[s][t], p[b * K + t]);
                 }
             }
         }
@@ -315,7 +318,7 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream(
         stream_rows<T, K, REBUILD, false>(D, g.ldd, AL, Uf, i_lo + wave, i_hi, jb, nvalid, zeta, bl, vt, y2, res,
                                           amax, P1t, lane);
 
-    // Y2 partial: sum the four waves' column partials through LDS.
+    // E^T Uf partial: sum the four waves' column partials through LDS.
     __shared__ Acc sm[STREAM_TN * K];
     __shared__ double red[STREAM_WAVES];
     for (int w = 0; w < STREAM_WAVES; ++w) {

@@ -1,20 +1,21 @@
-// The streaming pass with the product Y1 = Z V_f on the matrix cores (the
+// The streaming pass with the row product E V_f on the matrix cores (the
 // mixed-precision form). Per element of D, in FP32 on the vector ALUs, as in
 // the FP32 pass: the rank-K rebuild of L, the threshold T_zeta, the residual
-// (Section 2.1 and Algorithm 1), and the column product Y2 = Z^T U_f, which
-// each lane accumulates over rows for its own four columns. Y1 needs the sum
-// over columns, which on the vector ALUs costs a cross-lane reduction per row;
-// here the thresholded rows of Z are rounded to BF16 into LDS and Y1 runs as
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation (V_f rounded to BF16 too).
-// Only Y1 loses precision (BF16 operands, ~2^-9 relative per term); the
-// threshold decisions, the residual, err_k and Y2 are the FP32 ones. The
-// library switches to the FP32 pass once err_k falls below a set level.
+// part E = D - L - S (Section 2.1 and Algorithm 1), and the column product
+// E^T U_f, which each lane accumulates over rows for its own four columns. The
+// row product needs the sum over columns, which on the vector ALUs costs a
+// cross-lane reduction per row; here the rows of E are rounded to BF16 into
+// LDS and E V_f runs as v_mfma_f32_16x16x32_bf16 with FP32 accumulation (V_f
+// rounded to BF16 too). As in the FP32 pass, the gather adds the rank-K part
+// L V_f exactly, so only E V_f carries the BF16 rounding (~2^-9 relative per
+// term of E, whose size is the residual): the error of Y1 = Z V_f falls with
+// err_k. The threshold decisions, the residual, err_k and Y2 are the FP32 ones.
 //
 // Layout: workgroup of 4 waves, tile TM rows x 256 columns; each wave takes
 // blocks of 16 rows (rows i0 + 16w, i0 + 16(w + 4), ...). Phase A: the lane
 // owns columns 4l..4l+3, loads mx_batch(K) rows at a time (the next batch in
-// flight), and writes BF16 Z row-major into its wave's LDS block (row pitch
-// 260 BF16: the pad spreads the row reads over the banks). Phase B: Y1 of the
+// flight), and writes BF16 E row-major into its wave's LDS block (row pitch
+// 260 BF16: the pad spreads the row reads over the banks). Phase B: E V_f of the
 // 16 rows, eight MFMAs over the 32-column blocks of the tile, A read from LDS
 // (8 consecutive columns per lane). MFMA 16x16x32 lane layout: A row l%16,
 // k = 8(l/16)+q; B column l%16, k = 8(l/16)+q; C column l%16, rows 4(l/16)+r.
@@ -71,7 +72,7 @@ __device__ inline void mx_load_batch(const float* __restrict__ D, int64_t ldd, i
     }
 }
 
-// Threshold, residual and Y2 of one batch; Z in BF16 into the wave's LDS block.
+// Threshold, residual and E^T U_f of one batch; E in BF16 into the wave's LDS block.
 // CHECK: some rows of the batch may lie past i_hi (wave-uniform choice); a
 // batch inside the tile loads its row operands without per-row conditions.
 template <int K, int NBT, bool REBUILD, bool CHECK>
@@ -88,7 +89,7 @@ __device__ inline void mx_compute_batch(const float (&d)[NBT][4], const float* _
             al[t] = (REBUILD && (!CHECK || i < i_hi)) ? AL[(size_t)i * K + t] : 0.f;
             ut[t] = (!CHECK || i < i_hi) ? Uf[(size_t)i * K + t] : 0.f;
         }
-        float z[4];
+        float ev[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const float dv = d[b][s];
@@ -100,15 +101,15 @@ __device__ inline void mx_compute_batch(const float (&d)[NBT][4], const float* _
                 amax = fmaxf(amax, fabsf(x));
             }
             const bool big = fabsf(x) > zeta;   // S_ij = x
-            const float e = big ? 0.f : x;
+            const float e = big ? 0.f : x;      // entry of E = D - L - S
             rs = fmaf(e, e, rs);
-            z[s] = big ? dv - x : dv;
+            ev[s] = e;
 #pragma unroll
-            for (int t = 0; t < K; ++t) y2[s][t] = fmaf(z[s], ut[t], y2[s][t]);
+            for (int t = 0; t < K; ++t) y2[s][t] = fmaf(ev[s], ut[t], y2[s][t]);
         }
         uint2 w;
-        w.x = pack2(z[0], z[1]);
-        w.y = pack2(z[2], z[3]);
+        w.x = pack2(ev[0], ev[1]);
+        w.y = pack2(ev[2], ev[3]);
         *reinterpret_cast<uint2*>(zl + (r_local + b) * MX_PITCH + 4 * lane) = w;
     }
 }
