@@ -90,6 +90,41 @@ __device__ __forceinline__ void rows_outer_sum(const double (&a)[K], const doubl
     __syncthreads();
 }
 
+// Two such sums with a shared right factor in one pass: dst1 = sum a1 (x) b,
+// dst2 = sum a2 (x) b. sa1, sa2, sb: LDS scratch of NR*K doubles each.
+template <int K, int NR, int NT>
+__device__ __forceinline__ void rows_outer_sum2(const double (&a1)[K], const double (&a2)[K], const double (&b)[K],
+                                                bool writer, int slot, double* sa1, double* sa2, double* sb,
+                                                double* __restrict__ dst1, double* __restrict__ dst2) {
+    constexpr int E = 2 * K * K;
+    constexpr int G0 = pow2_floor(NT / E > 0 ? NT / E : 1);
+    constexpr int G = G0 > 16 ? 16 : G0;
+    constexpr int STEP = NT / G;
+    if (writer) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            sa1[slot * K + t] = a1[t];
+            sa2[slot * K + t] = a2[t];
+            sb[slot * K + t] = b[t];
+        }
+    }
+    __syncthreads();
+    const int sub = threadIdx.x % G;
+    for (int x0 = threadIdx.x / G; x0 < (E + STEP - 1) / STEP * STEP; x0 += STEP) {
+        const int x = x0 < E ? x0 : E - 1;   // whole groups stay in the loop for the DPP sum
+        const bool second = x >= K * K;
+        const int e = second ? x - K * K : x;
+        const double* sa = second ? sa2 : sa1;
+        const int t1 = e / K, t2 = e % K;
+        double acc = 0.0;
+#pragma unroll 4
+        for (int r = sub; r < NR; r += G) acc = fma(sa[r * K + t1], sb[r * K + t2], acc);
+        acc = group_sum<G>(acc);
+        if (sub == 0 && x0 < E) (second ? dst2 : dst1)[e] = acc;
+    }
+    __syncthreads();
+}
+
 __device__ inline bool is_finite_pos(double x) { return x > 0.0 && x < 1e300; }
 constexpr double MLP_O_CLIP = 5.0;   // the correction exp(o) stays within e^-5 .. e^5
 
@@ -322,7 +357,7 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     static_assert(FB % VW == 0 && NWG >= 1, "tile block of the gather");
     typedef typename Vec16<Acc>::type VecT;
     // LDS: the groups' tile sums, later the row vectors of the products
-    constexpr int NSH = NWG * FB > 2 * FB ? NWG * FB : 2 * FB;
+    constexpr int NSH = NWG * FB > 3 * FB ? NWG * FB : 3 * FB;
     __shared__ double shbuf[NSH];
     double* gsum = shbuf;
     double* sa = shbuf;
@@ -394,8 +429,10 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     }
     double* gp = a.gpart + (size_t)blockIdx.x * GPART_STRIDE;
     const bool writer = chunk == 0;   // y and f are zero unless this lane holds a valid row
-    rows_outer_sum<K, RPB, GATHER_THREADS>(f, y, writer, slot, sa, sb, gp);      // U_f^T Y1 or V_f^T Y2
-    if (GRAM) rows_outer_sum<K, RPB, GATHER_THREADS>(y, y, writer, slot, sa, sb, gp + KMAX * KMAX);
+    if (GRAM)   // U_f^T Y1 (V_f^T Y2) and Gram(Y1) (Gram(Y2))
+        rows_outer_sum2<K, RPB, GATHER_THREADS>(f, y, y, writer, slot, sa, shbuf + 2 * FB, sb, gp, gp + KMAX * KMAX);
+    else
+        rows_outer_sum<K, RPB, GATHER_THREADS>(f, y, writer, slot, sa, sb, gp);   // U_f^T Y1 or V_f^T Y2
     if (!last_block_arrives(&ctrl->cnt[CNT_GATHER], &flag)) return;
 
     // ---- last workgroup: all threads sum the partials, then one wave ----
@@ -544,7 +581,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
         __threadfence_system();
     }
     if (from_m && !ctrl->active) return;
-    __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K];
+    __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K], sc[PANEL_THREADS * K];
     __shared__ double e1[K * K], e2[K * K], sig[K];
     __shared__ int flag;
     const bool main_stage = !from_m || ctrl->stage == STAGE_MAIN;
@@ -641,10 +678,12 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
         }
     }
     double* gp = a.gpart + (size_t)blockIdx.x * GPART_STRIDE;
-    rows_outer_sum<K, PANEL_THREADS, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, gp);
-    // AL^T U_f and BL^T V_f for the gather of the next pass (main stage: the
-    // next pass rebuilds L)
-    if (main_stage) rows_outer_sum<K, PANEL_THREADS, PANEL_THREADS>(lf, gv, true, threadIdx.x, sa, sb, gp + KMAX * KMAX);
+    // Gram of the new basis; in the main stage (the next pass rebuilds L) also
+    // AL^T U_f and BL^T V_f for the gather of the next pass
+    if (main_stage)
+        rows_outer_sum2<K, PANEL_THREADS, PANEL_THREADS>(gv, lf, gv, true, threadIdx.x, sa, sc, sb, gp, gp + KMAX * KMAX);
+    else
+        rows_outer_sum<K, PANEL_THREADS, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, gp);
     if (!last_block_arrives(&ctrl->cnt[CNT_UPDATE], &flag)) return;
     __shared__ double gg[4 * K * K], rr[K * K], ri[K * K], rr2[K * K], ri2[K * K], part[PANEL_THREADS];
     double* g = gg;
