@@ -193,8 +193,10 @@ int rpca_materialize(const void *D, const rpca_params *p, const rpca_state *st,
  *   Y1 = Z V_t   (device m x r, FP64)    Y2 = Z^T U_t (device n x r, FP64)
  *   *resid2 = sum over |x_ij| <= zeta of x_ij^2   (host scalar),
  * where U_t (m x r) and V_t (n x r) are device FP64 bases. Inputs are rounded
- * to dtype before the pass, as inside rpca_step; with RPCA_FLAG_MIXED, Y1 is
- * the BF16 matrix-core product. */
+ * to dtype before the pass, as inside rpca_step. As there, the pass forms the
+ * products of the residual part E = D - L - S and the rank-r parts L V_t and
+ * L^T U_t are added in FP64 from the rounded factors; with RPCA_FLAG_MIXED,
+ * E V_t is the BF16 matrix-core product. */
 int rpca_tangent_products(const void *D, const rpca_params *p,
                           const double *A_L, const double *B_L, double zeta,
                           const double *U_t, const double *V_t,
