@@ -95,7 +95,7 @@ struct Ctrl {
     double max_abs_D;    // max |D_ij| (from the init passes, where L = 0)
     double err_prev;     // err_{k-1} (fallback test of the learned schedule)
     int32_t learned_on;  // 1 while zeta_{k+1} comes from the threshold network
-    int32_t pad2_;
+    int32_t res_carried; // 1: the init stage continues the previous stage's iteration (res_prev is its)
     int32_t single;      // 1: D and the streamed factors are FP32
     int32_t pad_;
 };

@@ -267,13 +267,23 @@ __device__ __forceinline__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const
             double acc = 0.0;
             for (int t = 0; t < r; ++t) acc += fmax(g1[t * K + t], 0.0) + fmax(g2[t * K + t], 0.0);
             const double res = sg[0] > 0.0 ? sqrt(acc) / sg[0] : 0.0;
-            // Converged: below the stage's tolerance; or stalled (less than a
-            // halving per pass) within 100x of it, where rounding of the
+            // res measures the block this pass started from; the block it
+            // returns (the Ritz vectors of M) is better by about the contraction
+            // factor of the iteration, estimated from the last two passes.
+            // Converged: below the stage's tolerance; or that prediction for
+            // the returned block, with a margin of 10, below it once the
+            // iteration contracts steadily (third pass on, factor < 1/2), which
+            // saves the pass that would only confirm it; or stalled (less than
+            // a halving per pass) within 100x of it, where rounding of the
             // products limits the residual; or at the pass cap.
+            const double rho = res / ctrl->res_prev;
+            const bool steady = (ctrl->passes >= 3 || ctrl->res_carried) && rho < 0.5;
             const bool stall = ctrl->passes >= 3 && res > 0.5 * ctrl->res_prev;
             const bool capped = ctrl->passes >= ctrl->init_max_passes;
-            const bool conv_a = res <= ctrl->tol_res_a || (stall && res <= 100.0 * ctrl->tol_res_a) || capped;
-            const bool conv_b = res <= ctrl->tol_res_b || (stall && res <= 100.0 * ctrl->tol_res_b) || capped;
+            const bool conv_a = res <= ctrl->tol_res_a || (steady && 10.0 * res * rho <= ctrl->tol_res_a) ||
+                                (stall && res <= 100.0 * ctrl->tol_res_a) || capped;
+            const bool conv_b = res <= ctrl->tol_res_b || (steady && 10.0 * res * rho <= ctrl->tol_res_b) ||
+                                (stall && res <= 100.0 * ctrl->tol_res_b) || capped;
             const double res_last = res;
             ctrl->res_prev = res;
             if (ctrl->stage == STAGE_SIGMA_D && conv_a) {
@@ -292,6 +302,7 @@ __device__ __forceinline__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const
                     ctrl->stage = STAGE_INIT_Z;
                     ctrl->passes = 0;
                     ctrl->res_prev = s_empty ? res_last : 1e300;
+                    ctrl->res_carried = s_empty ? 1 : 0;
                 }
             } else if (ctrl->stage == STAGE_INIT_Z && conv_b) {
                 ctrl->zeta = ctrl->beta * sg[0];          // zeta_0 = beta sigma_1(D - S_{-1})
