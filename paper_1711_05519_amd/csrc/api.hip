@@ -208,7 +208,7 @@ void prof_drop_last() {
 
 int init_block_of(const rpca_params* p) {
     if (p->init_block > 0) return p->init_block;
-    int q = p->r + 1;   // at m = n = 10^4, r = 5: 6 passes of width 6, the fastest width measured
+    int q = p->r + 1;   // at m = n = 10^4, r = 5: 5 passes of width 6; the fastest width measured
     if (q > KMAX) q = KMAX;
     const int64_t lim = (p->m < p->n ? p->m : p->n) / 2;
     if (q > lim) q = (int)lim;
