@@ -184,7 +184,7 @@ __device__ __forceinline__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const
     // sigma_1)^2 are not rotated against each other: both end below the
     // dropping level below, and such a rotation moves no other column.
     const double neg2 = ctrl->sigma_dead * ctrl->sigma_dead / N;
-    const int sweeps = wave_jacobi_svd<N>(Ma, Mv, sg, Um, Vm, neg2);
+    const int sweeps = wave_jacobi_svd<N>(Ma, Mv, sg, Um, Vm, neg2, ctrl->single ? JACOBI_QUAD_F32 : JACOBI_QUAD);
     // Triplets whose singular value is at the rounding level of the products
     // (sigma_j <= sigma_dead * sigma_1) carry no information about the range
     // of P_T(Z): their vectors are noise and need not be orthogonal to U*, so

@@ -21,6 +21,9 @@ constexpr int JACOBI_MAX_SWEEPS = 40;
 // pair), the angles a further sweep would take are of the order
 // JACOBI_QUAD^2, and the confirming sweep is skipped.
 constexpr double JACOBI_QUAD = 1e-8;
+// The same for M formed from FP32 products: angles of the order 1e-12 change
+// the singular vectors far below the rounding of those products.
+constexpr double JACOBI_QUAD_F32 = 1e-6;
 constexpr double CHOL_DEAD_REL = 1e-26;
 
 // ---- single-wave helpers (the last workgroup's tail) ---------------------------
@@ -298,11 +301,13 @@ constexpr int pow2_floor(int x) { int p = 1; while (p * 2 <= x) p *= 2; return p
 // ||a||^2 <= neg2 ||A||_F^2 (columns the caller discards: a rotation never
 // raises the smaller norm of a pair). Sweeps stop when no pair was rotated, or
 // (QUAD_STOP) after a sweep whose rotation angles were all below
-// JACOBI_QUAD; callers that difference the result keep the confirming sweep. On return
+// quad (default JACOBI_QUAD); callers that difference the result keep the
+// confirming sweep. On return
 // sig[] is descending and Uo/Vo hold the left/right singular vectors as
 // columns (column-major). Returns the sweep count.
 template <int N, bool QUAD_STOP = true>
-__device__ __forceinline__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, double* Vo, double neg2 = 0.0) {
+__device__ __forceinline__ int wave_jacobi_svd(double* A, double* V, double* sig, double* Uo, double* Vo, double neg2 = 0.0,
+                                               double quad = JACOBI_QUAD) {
     static_assert(N % 2 == 0 && N <= 2 * KMAX, "even N up to 2*KMAX");
     constexpr int NP = N / 2;
     constexpr int LP0 = pow2_floor(WAVE / NP);
@@ -356,7 +361,7 @@ __device__ __forceinline__ int wave_jacobi_svd(double* A, double* V, double* sig
                     const double ic = rsqrt(c2);
                     const double c = c2 * ic;
                     const double s = (dl >= 0.0 ? ga : -ga) * rh * ic;
-                    large = large || fabs(s) > JACOBI_QUAD;
+                    large = large || fabs(s) > quad;
 #pragma unroll
                     for (int u = 0; u < E; ++u) {
                         const int e = g + LP * u;
