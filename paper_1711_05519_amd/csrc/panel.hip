@@ -465,10 +465,21 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
         w_fetch<K>(a.small->RUinv, ru_pre);
         w_fetch<K>(a.small->RVinv, rv_pre);
     }
+    // The single-wave tail works on a copy of the control block in LDS (no
+    // other workgroup or kernel touches it meanwhile), loaded with the other
+    // loads of this phase and written back whole at the end.
+    constexpr int CW = (int)(sizeof(Ctrl) / 4);
+    static_assert(sizeof(Ctrl) % 4 == 0 && CW <= WAVE, "one word of the control block per lane");
+    __shared__ Ctrl cl;
+    uint32_t cword = 0;
+    if (threadIdx.x < CW) cword = reinterpret_cast<const uint32_t*>(ctrl)[threadIdx.x];
     block_sum_partials<K * K, GRAM ? 4 : 2, GATHER_THREADS>(a.gpart, gU, gV, sums, part);
     block_resid<GATHER_THREADS>(a.resid, a.n_tiles, sigma_stage, rv_, rw_, part, rsum);
     if (threadIdx.x >= WAVE) return;
     const int lane = lane_id();
+    if (lane < CW) reinterpret_cast<uint32_t*>(&cl)[lane] = cword;
+    Ctrl* const cg = ctrl;   // the control block in device memory
+    ctrl = &cl;
     w_put<K>(ru_pre, ru);
     w_put<K>(rv_pre, rv);
     // C* = R_U^{-T} (U_f^T Y1) R_V^{-1},  C2 = R_V^{-T} (V_f^T Y2) R_U^{-1}
@@ -515,6 +526,8 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
         wave_sync();
         w_svd_tail<K>(a, ctrl, cs, c2, g1, g2, ru, rv, true);
     }
+    wave_sync();
+    if (lane < CW) reinterpret_cast<uint32_t*>(cg)[lane] = reinterpret_cast<const uint32_t*>(&cl)[lane];
 }
 
 // ---- kernel 2 (FP64): explicit complements W1, W2, their Grams, 2K x 2K step -
