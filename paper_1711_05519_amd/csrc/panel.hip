@@ -81,9 +81,17 @@ __device__ __forceinline__ void rows_outer_sum(const double (&a)[K], const doubl
     for (int e0 = threadIdx.x / G; e0 < (K * K + STEP - 1) / STEP * STEP; e0 += STEP) {
         const int e = e0 < K * K ? e0 : K * K - 1;   // whole groups stay in the loop for the DPP sum
         const int t1 = e / K, t2 = e % K;
-        double acc = 0.0;
-#pragma unroll 4
-        for (int r = sub; r < NR; r += G) acc = fma(sa[r * K + t1], sb[r * K + t2], acc);
+        // four interleaved accumulators (shorter dependence chains), summed in a fixed order
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+        int r = sub;
+        for (; r + 3 * G < NR; r += 4 * G) {
+            c0 = fma(sa[r * K + t1], sb[r * K + t2], c0);
+            c1 = fma(sa[(r + G) * K + t1], sb[(r + G) * K + t2], c1);
+            c2 = fma(sa[(r + 2 * G) * K + t1], sb[(r + 2 * G) * K + t2], c2);
+            c3 = fma(sa[(r + 3 * G) * K + t1], sb[(r + 3 * G) * K + t2], c3);
+        }
+        for (; r < NR; r += G) c0 = fma(sa[r * K + t1], sb[r * K + t2], c0);
+        double acc = (c0 + c1) + (c2 + c3);
         acc = group_sum<G>(acc);
         if (sub == 0 && e0 < K * K) dst[e] = acc;
     }
@@ -116,9 +124,16 @@ __device__ __forceinline__ void rows_outer_sum2(const double (&a1)[K], const dou
         const int e = second ? x - K * K : x;
         const double* sa = second ? sa2 : sa1;
         const int t1 = e / K, t2 = e % K;
-        double acc = 0.0;
-#pragma unroll 4
-        for (int r = sub; r < NR; r += G) acc = fma(sa[r * K + t1], sb[r * K + t2], acc);
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+        int r = sub;
+        for (; r + 3 * G < NR; r += 4 * G) {
+            c0 = fma(sa[r * K + t1], sb[r * K + t2], c0);
+            c1 = fma(sa[(r + G) * K + t1], sb[(r + G) * K + t2], c1);
+            c2 = fma(sa[(r + 2 * G) * K + t1], sb[(r + 2 * G) * K + t2], c2);
+            c3 = fma(sa[(r + 3 * G) * K + t1], sb[(r + 3 * G) * K + t2], c3);
+        }
+        for (; r < NR; r += G) c0 = fma(sa[r * K + t1], sb[r * K + t2], c0);
+        double acc = (c0 + c1) + (c2 + c3);
         acc = group_sum<G>(acc);
         if (sub == 0 && x0 < E) (second ? dst2 : dst1)[e] = acc;
     }
@@ -355,6 +370,13 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
             for (int t = 0; t < K; ++t) lraw[t] = LF[(size_t)row * K + t];
         }
     }
+    // BL^T V_f (U side) or AL^T U_f (V side) for the rank-K part, one entry
+    // per thread, put into LDS with the tile sums
+    static_assert(K * K <= GATHER_THREADS, "one entry of the cross product per thread");
+    __shared__ double gk[K * K];
+    double gkv = 0.0;
+    if (a.lcorr && (int)threadIdx.x < K * K)
+        gkv = (uside ? a.small->GBV : a.small->GAU)[(threadIdx.x / K) * KMAX + threadIdx.x % K];
     // Sum over the tiles of the streaming pass. Per tile, the rows of this
     // workgroup are one contiguous block of RPB * K values ([row][t]), read as
     // 16-byte vectors: NWG groups of NV threads each take every NWG-th tile
@@ -406,6 +428,7 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
             for (int j = 0; j < VW; ++j) gsum[grp * FB + vi * VW + j] = acc[j];
         }
     }
+    if (a.lcorr && (int)threadIdx.x < K * K) gk[threadIdx.x] = gkv;
     __syncthreads();
     double y[K];
 #pragma unroll
@@ -418,12 +441,11 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     __syncthreads();   // gsum is reused as sa, sb below
     if (holder && a.lcorr) {
         // Y1 = E V_f + AL (BL^T V_f),  Y2 = E^T U_f + BL (AL^T U_f)
-        const double* G = uside ? a.small->GBV : a.small->GAU;
 #pragma unroll
         for (int t = 0; t < K; ++t) {
             double c = 0.0;
 #pragma unroll
-            for (int u = 0; u < K; ++u) c = fma(static_cast<double>(lraw[u]), G[u * KMAX + t], c);
+            for (int u = 0; u < K; ++u) c = fma(static_cast<double>(lraw[u]), gk[u * K + t], c);
             y[t] += c;
         }
     }
@@ -712,7 +734,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
     __shared__ double gg[4 * K * K], rr[K * K], ri[K * K], rr2[K * K], ri2[K * K], part[PANEL_THREADS];
     double* g = gg;
     double* gb = gg + K * K;
-    if (main_stage) block_sum_partials<K * K, 4, PANEL_THREADS>(a.gpart, a.gU, a.gV, gg, part);
+    if (main_stage) block_sum_partials<K * K, 4, PANEL_THREADS, 32>(a.gpart, a.gU, a.gV, gg, part);
     else block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, a.gU, a.gV, gg, part);
     if (threadIdx.x >= WAVE) return;
     const bool exact = a.mode == UPDATE_ENTER_EXACT;

@@ -99,15 +99,15 @@ __device__ inline void w_mm2(const double* A, const double* B, double* C, const 
 // The whole workgroup (NT threads) takes part. Thread t takes pair
 // q = t % PAIRS (job q / E, entry q % E) and split s = t / PAIRS and sums the
 // partials b = s, s + S, ... in order; the S split sums of a pair are then
-// added in order of s. Up to 16 loads per thread are in flight at once, so a
-// round over up to 16 S partials costs one memory latency. part: NT doubles
+// added in order of s. Up to L loads per thread are in flight at once, so a
+// round over up to L S partials costs one memory latency. part: NT doubles
 // of LDS.
-template <int E, int J, int NT>
+template <int E, int J, int NT, int L = 16>
 __device__ __forceinline__ void block_sum_partials(const double* __restrict__ gpart, int gU, int gV, double* out, double* part) {
     constexpr int PAIRS = J * E;
     constexpr int PR = PAIRS >= NT ? NT : PAIRS;   // pairs per round
     constexpr int S = NT / PR;                     // splits per pair
-    constexpr int L = 16;                          // loads in flight per thread
+    // L: loads in flight per thread
     const int t = threadIdx.x;
     for (int q0 = 0; q0 < PAIRS; q0 += PR) {
         const int sp = t / PR, q = q0 + t % PR;
