@@ -32,6 +32,14 @@
  * - Return value: RPCA_OK (0) or RPCA_MAXITER (1) on success, a negative
  *   RPCA_E* code on failure. Arguments are validated before any launch; a
  *   failed validation leaves every output untouched.
+ * - The data D itself is validated by the first pass over it, which already
+ *   forms ||D||_F^2 (the denominator of err_k, Section 3): rpca_init and
+ *   rpca_solve return RPCA_EINVAL when ||D||_F = 0 or when the sum is not
+ *   finite (a NaN or infinite entry, or an entry whose square overflows the
+ *   dtype); rpca_step returns RPCA_EINVAL when the residual of its first pass
+ *   (at the given state) is not finite. In these cases the caller's state is
+ *   left untouched. A residual that becomes non-finite later inside
+ *   rpca_solve's loop returns RPCA_EBREAKDOWN.
  */
 #ifndef RPCA_H
 #define RPCA_H
@@ -50,6 +58,7 @@ extern "C" {
 #define RPCA_EWORKSPACE  -2   /* workspace missing or smaller than required            */
 #define RPCA_EHIP        -3   /* a HIP runtime call failed (see rpca_last_hip_error)   */
 #define RPCA_ENODEV      -4   /* no gfx950 device is current                           */
+#define RPCA_EBREAKDOWN  -5   /* a residual sum became non-finite inside the iteration */
 
 /* ---- element types of D ------------------------------------------------ */
 #define RPCA_F64 0            /* D (and dense L/S outputs) are double                  */

@@ -2,7 +2,7 @@
 
 Not part of the paper: the paper fixes the threshold schedule
 zeta_{k+1} = beta (sigma_{r+1} + gamma^{k+1} sigma_1) (Algorithm 1, Section 2.1).
-This module is the plain reference for two additions built on top of it:
+This module is the plain reference for the additions built on top of it:
 
 * a small multilayer perceptron that maps features of the current iterate to a
   correction of the threshold, zeta_k = zeta_paper * exp(clip(o, -5, 5))
@@ -11,7 +11,9 @@ This module is the plain reference for two additions built on top of it:
 * one AccAltProj iteration with the hard threshold T_zeta replaced by the
   relaxation s(x) = x * logistic((|x| - zeta) / tau), which tends to T_zeta as
   tau -> 0, together with the derivative of a loss of the next iterate with
-  respect to zeta.
+  respect to zeta;
+* Algorithm 1 whose thresholds come from the network, with the fallback to
+  the paper's schedule once err_k stops decreasing (learned_solve).
 
 Everything is dense float64 and literal: the derivative of the rank-r
 truncation H_r is the first-order perturbation of a full dense SVD, written
@@ -20,6 +22,9 @@ learned threshold); the tests pin them by central finite differences, closed
 forms and limits instead.
 """
 from __future__ import annotations
+
+import dataclasses
+import math
 
 import numpy as np
 
@@ -175,3 +180,79 @@ def step_loss_grad_zeta(D, st, zeta, tau, p, L_true) -> float:
     dPZ = A.tangent_projection(Ut, Vt, dZ)
     dL1 = truncation_derivative(PZ, dPZ, p.r)
     return float(2.0 * np.sum((L1 - L_true) * dL1) / np.sum(L_true ** 2))
+
+
+# ------------------------------------------- Algorithm 1 with the network ---
+
+K_FEAT = 15          # iteration count that normalises the first feature
+
+
+@dataclasses.dataclass
+class LearnedSolve:
+    state: A.State
+    err_hist: list
+    zeta_hist: list
+    sigma_hist: list     # sigma_M of P_T(D - S_k) for every executed body (k = 0, 1, ...)
+    learned_hist: list   # whether zeta_{k+1} came from the network
+    iterations: int
+    converged: bool
+
+
+def learned_solve(D: np.ndarray, p: A.Params, theta: np.ndarray | None, max_iter: int | None = None,
+                  fixed_iters: int | None = None) -> LearnedSolve:
+    """Algorithm 1 (with the initialisation of Algorithm 3) in which the
+    threshold of every body may come from the network:
+
+      zeta_{k+1} = zeta_paper * exp(clip(o_k, -5, 5)),
+      zeta_paper = beta (sigma_{r+1} + gamma^{k+1} sigma_1)   (Algorithm 1),
+      o_k = network(phi_k),  phi_k = ((k + 1) / 15, log(sigma_{r+1} / sigma_1),
+                                      log err_k, log(sigma_1 / ||D||_F)),
+
+    with sigma_1, sigma_{r+1} those of P_T(D - S_k) (the 2r x 2r matrix of
+    Section 2.1). Fallback latch: once err_k >= err_{k-1} (k >= 1), or once the
+    network's threshold is not a positive finite number, every later threshold
+    is the paper's. theta None means the paper's schedule throughout. The
+    stopping rule is Section 3's (err_k < tol or k = max_iter); fixed_iters
+    runs exactly that many bodies instead. theta is used as given (the network
+    of the library holds FP32 parameters: pass them rounded to FP32)."""
+    if max_iter is None:
+        max_iter = p.max_iter
+    normD = A.frobenius(D)
+    st = A.initialize(D, p, normD)
+    err_hist, zeta_hist, sigma_hist, learned_hist = [st.err], [st.zeta], [], []
+    on = theta is not None
+    err_prev = math.inf
+    while True:
+        k = st.k
+        if on and k >= 1 and not (st.err < err_prev):
+            on = False                       # err stopped decreasing: the paper's schedule from here on
+        err_prev = st.err
+        if fixed_iters is not None:
+            if k >= fixed_iters:
+                break
+        elif st.err < p.tol or k >= max_iter:
+            break
+        # one body of Algorithm 1: Trim, H_r(P_T(D - S_k)), then the threshold
+        Sk = A.hard_threshold(D - st.L(), st.zeta)
+        Ut, Vt = A.trimmed_bases(st.U, st.V, p.mu, p.r)
+        ts = A.tangent_svd(Ut, Vt, D - Sk, p.r)
+        zeta = A.next_zeta(p.beta, p.gamma, k, ts.sigma_M, p.r)
+        used = False
+        if on:
+            phi = features(k + 1, K_FEAT, float(ts.sigma_M[0]), float(ts.sigma_M[p.r]), st.err, normD)
+            o, _ = mlp_forward(theta, phi)
+            zl = zeta_of(o, zeta) if o == o else math.nan
+            if math.isfinite(zl) and zl > 0.0:
+                zeta, used = zl, True
+            else:
+                on = False
+        nxt = A.State(U=ts.U, sigma=ts.sigma, V=ts.V, zeta=zeta, k=k + 1, sigma_M=ts.sigma_M)
+        L1 = nxt.L()
+        nxt.err = A.relative_error(D, L1, A.hard_threshold(D - L1, zeta), normD)
+        st = nxt
+        err_hist.append(st.err)
+        zeta_hist.append(st.zeta)
+        sigma_hist.append(ts.sigma_M.copy())
+        learned_hist.append(used)
+    return LearnedSolve(state=st, err_hist=err_hist, zeta_hist=zeta_hist, sigma_hist=sigma_hist,
+                        learned_hist=learned_hist, iterations=st.k, converged=bool(st.err < p.tol))

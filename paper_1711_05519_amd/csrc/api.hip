@@ -605,6 +605,7 @@ int run_init(const Ctx& c, const void* D, rpca_state* st, Ctrl* ctrl_out) {
     RPCA_TRY(rc);
     Ctrl now;
     RPCA_TRY(read_ctrl(c, &now));
+    if (now.nonfinite) return RPCA_EINVAL;               // ||D||_F = 0 or a non-finite entry
     if (now.stage < STAGE_INIT_DONE) return RPCA_EHIP;   // unreachable: the pass cap forces convergence
     // L_0: the leading r columns of the converged block
     RPCA_TRY(enqueue_enter(c, c.at<double>(c.L.off_Unew), c.at<double>(c.L.off_Vnew), P,
@@ -676,6 +677,7 @@ const char* rpca_strerror(int status) {
         case RPCA_EWORKSPACE: return "workspace missing, misaligned or too small";
         case RPCA_EHIP: return "HIP runtime error";
         case RPCA_ENODEV: return "current device is not a gfx950 GPU";
+        case RPCA_EBREAKDOWN: return "non-finite residual inside the iteration (numerical breakdown)";
         default: return "unknown status";
     }
 }
@@ -699,6 +701,7 @@ int rpca_init(const void* D, const rpca_params* p, rpca_state* st, void* ws, siz
     RPCA_TRY(threshold_pass(c, D, true));
     Ctrl t;
     RPCA_TRY(read_ctrl(c, &t));
+    if (t.nonfinite) return RPCA_EBREAKDOWN;
     fill_state(st, t);
     st->init_passes = ic.total_passes;
     return RPCA_OK;
@@ -795,6 +798,8 @@ public:
         RPCA_TRY(rc_);
         Ctrl fin;
         RPCA_TRY(read_ctrl(c_, &fin));
+        if (fin.nonfinite == 1) return RPCA_EINVAL;       // ||D||_F = 0 or a non-finite entry of D
+        if (fin.nonfinite) return RPCA_EBREAKDOWN;        // a non-finite residual inside the loop
         if (fin.stage != STAGE_MAIN) return RPCA_EHIP;   // unreachable: the pass cap forces convergence
         fill_state(st_, fin);
         st_->init_passes = fin.total_passes;
@@ -835,7 +840,10 @@ private:
     // The record of body b - 1 (queued before body b).
     int on_record(const BodyRecord& hs) {
         if (!in_loop_) {
-            if (hs.stage >= STAGE_INIT_DONE) {
+            if (hs.stage == STAGE_FAILED) {
+                prof_drop_last();   // body b ran after the failed pass: a no-op
+                stopped_ = true;
+            } else if (hs.stage >= STAGE_INIT_DONE) {
                 prof_drop_last();   // body b ran after the stage changed: a no-op
                 // L_0: the leading r columns of the converged block; Trim and bases
                 RPCA_TRY(enqueue_enter(c_, c_.at<double>(c_.L.off_Unew), c_.at<double>(c_.L.off_Vnew), P_,
@@ -982,6 +990,7 @@ int compute_normD2(const Ctx& c, const void* D, double* out) {
     RPCA_TRY(threshold_pass(c, D, false));
     Ctrl t;
     RPCA_TRY(read_ctrl(c, &t));
+    if (t.nonfinite) return RPCA_EINVAL;
     *out = t.normD2;
     return RPCA_OK;
 }
@@ -1006,6 +1015,9 @@ int rpca_step(const void* D, const rpca_params* p, rpca_state* st, void* ws, siz
     RPCA_TRY(threshold_pass(c, D, true));
     Ctrl t;
     RPCA_TRY(read_ctrl(c, &t));
+    // a non-finite residual of the pass at L_k (D or the given state) stopped
+    // the body before its update: the state is untouched
+    if (t.nonfinite) return RPCA_EINVAL;
     fill_state(st, t);
     return RPCA_OK;
 }

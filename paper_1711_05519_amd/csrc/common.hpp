@@ -34,6 +34,7 @@ enum Stage : int {
     STAGE_INIT_Z = 1,    // init: subspace iteration on D - T_{zeta_-1}(D)
     STAGE_INIT_DONE = 2, // init converged; host switches to rank-r kernels
     STAGE_MAIN = 3,      // AccAltProj loop
+    STAGE_FAILED = 4,    // init stopped: ||D||_F = 0 or a non-finite entry in D
 };
 
 // Which loop a kernel launch belongs to (gating of speculatively queued bodies).
@@ -97,7 +98,8 @@ struct Ctrl {
     int32_t learned_on;  // 1 while zeta_{k+1} comes from the threshold network
     int32_t res_carried; // 1: the init stage continues the previous stage's iteration (res_prev is its)
     int32_t single;      // 1: D and the streamed factors are FP32
-    int32_t pad_;
+    int32_t nonfinite;   // 1: ||D||_F^2 was zero or not finite (bad input);
+                         // 2: a later residual sum was not finite (bad state or breakdown)
 };
 
 // Small FP64 matrices shared between kernels (all K x K, row-major, ld = KMAX).

@@ -1,6 +1,8 @@
 // The threshold network of the learned schedule (not part of the paper):
 // o = w3 . relu(W2 relu(W1 phi + b1) + b2) + b3 with phi in R^4, 32 hidden
-// units per layer, and zeta = beta sigma_1 softplus(o). Parameters are one
+// units per layer; the loop uses it as a multiplicative correction of
+// Algorithm 1's threshold, zeta = beta (sigma_{r+1} + gamma^{k+1} sigma_1)
+// exp(clip(o, -5, 5)) (the single-wave tail of the gather). Parameters are one
 // FP32 vector of MLP_PARAMS values: W1 (32 x 4, row-major), b1, W2 (32 x 32),
 // b2, w3, b3. These kernels train it: a batched forward pass, the gradient
 // of sum_b g_b o_b summed over the batch in a fixed order, and Adam.

@@ -344,7 +344,12 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
     constexpr int RPB = GATHER_THREADS / GATHER_SPLIT;   // rows per workgroup
     constexpr bool GRAM = sizeof(T) == 4;
     Ctrl* ctrl = a.ctrl;
-    if (!body_runs(ctrl, a.body)) return;
+    if (!body_runs(ctrl, a.body)) {
+        // A body queued past the end of its loop: the complement and update
+        // kernels that follow read `active` and must do nothing either.
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->active = 0;
+        return;
+    }
     __shared__ int flag;
     const int gU = (a.m + RPB - 1) / RPB;
     const bool uside = (int)blockIdx.x < gU;
@@ -517,7 +522,16 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
             ctrl->normD2 = rs;   // zeta = +inf: the residual is ||D||_F^2
             ctrl->max_abs_D = mx;
         }
-        if (ctrl->stage == STAGE_MAIN) {
+        // A residual sum that is NaN or infinite comes from a non-finite entry
+        // of D (or of the state a single step starts from); ||D||_F = 0 leaves
+        // err_k = 0 / 0. Either ends the call: nothing queued after it runs.
+        const bool bad = !(rs <= 1.7976931348623157e308) || (sigma_stage && !(rs > 0.0));
+        if (bad) {
+            ctrl->nonfinite = sigma_stage ? 1 : 2;
+            ctrl->done = 1;
+            ctrl->stopped_by_tol = 0;
+            if (ctrl->stage != STAGE_MAIN) ctrl->stage = STAGE_FAILED;
+        } else if (ctrl->stage == STAGE_MAIN) {
             const double err = sqrt(rs / ctrl->normD2);
             ctrl->err = err;
             const int k = ctrl->k;

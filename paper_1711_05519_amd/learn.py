@@ -13,8 +13,12 @@ through d zeta_k / d o_k = zeta_k (inside the clip) and the network's own
 backward kernel, with Adam. The state reached by the unrolled iterations is
 data for the next iteration, not differentiated through (truncated back-
 propagation of one step). tau is annealed as tau_e = tau0 * 0.5^e (relative
-to zeta). All arithmetic runs in the library's kernels; this module only
-sequences the calls.
+to zeta). The passes over D, the relaxed iteration, its adjoint and the
+network's forward, backward and Adam update run in the library's kernels;
+this module sequences the calls and does the scalar bookkeeping on the host
+between them (Algorithm 1's threshold for the next step from the sigma
+values a step returns, the clip of the correction and the chain rule
+d log loss / d o = (d loss / d zeta) zeta / loss, a few flops per step).
 """
 from __future__ import annotations
 

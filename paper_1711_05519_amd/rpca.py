@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librpca.so")
 
 RPCA_OK, RPCA_MAXITER = 0, 1
-RPCA_EINVAL, RPCA_EWORKSPACE, RPCA_EHIP, RPCA_ENODEV = -1, -2, -3, -4
+RPCA_EINVAL, RPCA_EWORKSPACE, RPCA_EHIP, RPCA_ENODEV, RPCA_EBREAKDOWN = -1, -2, -3, -4, -5
 RPCA_F64, RPCA_F32 = 0, 1
 RPCA_FLAG_NO_TRIM = 1
 RPCA_FLAG_MIXED = 2

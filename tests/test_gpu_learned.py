@@ -111,3 +111,88 @@ def test_shipped_network_converges_on_held_out_instances():
         say(f"held-out {i}: r={x.r} alpha={x.alpha:.3f} plain {ip.iterations} it, learned {il.iterations} it")
         assert il.status == R.RPCA_OK
         assert np.linalg.norm(Ll - x.L) / np.linalg.norm(x.L) <= 1e-4
+
+
+def _shipped():
+    path = os.path.join(os.path.dirname(LN.__file__), "zeta_mlp.npy")
+    return LN.load_theta(path)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_learned_solve_matches_oracle(dtype):
+    """The in-loop network (the single-wave tail's forward pass, the
+    exp(clip(o)) correction and the fallback latch) against the oracle's
+    Algorithm 1 with the same network (oracle.learned.learned_solve), shipped
+    parameters, on the 1000 x 1000 r = 5 workload: same iteration count,
+    thresholds and L_K within 1e-10 (FP64) / 1e-5 (FP32)."""
+    x = I.config_instance(1, keep_L=True)
+    f32 = dtype == torch.float32
+    tol = 1e-5 if f32 else 1e-6
+    D = x.D.astype(np.float32).astype(np.float64) if f32 else x.D
+    th = _shipped()
+    th_np = th.cpu().numpy().astype(np.float64)
+    import oracle as O
+    p = O.Params(r=x.r, beta=x.beta, beta_init=x.beta_init, gamma=x.gamma, mu=x.mu_in, tol=tol)
+    ref = Lr.learned_solve(D, p, th_np)
+    sv = R.Solver(torch.as_tensor(D, dtype=dtype, device="cuda"), x.r, x.beta, x.beta_init, x.gamma, x.mu_in,
+                  tol=tol, seed=7, learned=th)
+    info = sv.solve()
+    U, s, V = (t.cpu().numpy() for t in sv.L_factors())
+    L = (U * s) @ V.T
+    bar = 1e-5 if f32 else 1e-10
+    d = np.linalg.norm(L - ref.state.L()) / np.linalg.norm(ref.state.L())
+    say(f"learned {dtype}: iterations {info.iterations}/{ref.iterations}, network used for "
+        f"{sum(ref.learned_hist)} thresholds, rel L {d:.2e}")
+    assert info.status == R.RPCA_OK
+    assert info.iterations == ref.iterations
+    assert sum(ref.learned_hist) >= 2                    # the network set several thresholds
+    np.testing.assert_allclose(info.err_hist, ref.err_hist, rtol=1e-8 if not f32 else 1e-3)
+    assert d <= bar
+    # Thresholds. Both the paper's threshold beta (sigma_{r+1} + gamma^{k+1}
+    # sigma_1) and the network's feature log(sigma_{r+1} / sigma_1) use
+    # sigma_{r+1}, which falls toward the rounding level late in a solve
+    # (sigma_{r+1} / sigma_1 ~ 1e-5 .. 1e-13 here). Its absolute accuracy is
+    # about eta sigma_1: FP64 1e-8 (the Jacobi SVD of M leaves couplings below
+    # 1e-17 ||M||_F^2 unrotated, which resolves singular values to ~3e-9
+    # ||M||_F), FP32 1e-5 (the products' rounding). So zeta_{k+1} may move by
+    # eta sigma_1 / (sigma_{r+1} + gamma^{k+1} sigma_1) relative through the
+    # paper's term, plus |d o / d phi_1| eta sigma_1 / sigma_{r+1} through the
+    # feature when the network's output is not clipped.
+    eta = 1e-5 if f32 else 1e-8
+    nD = np.linalg.norm(D)
+    assert abs(info.zeta_hist[0] - ref.zeta_hist[0]) <= bar * ref.zeta_hist[0]
+    for k, sm in enumerate(ref.sigma_hist):
+        allowed = bar + eta * sm[0] / (sm[x.r] + x.gamma ** (k + 1) * sm[0])
+        if ref.learned_hist[k]:
+            phi = Lr.features(k + 1, Lr.K_FEAT, sm[0], sm[x.r], ref.err_hist[k], nD)
+            o = Lr.mlp_forward(th_np, phi)[0]
+            if abs(o) < Lr.O_CLIP:
+                h = np.array([0.0, 1e-6, 0.0, 0.0])
+                g1 = (Lr.mlp_forward(th_np, phi + h)[0] - Lr.mlp_forward(th_np, phi - h)[0]) / 2e-6
+                allowed += abs(g1) * eta * sm[0] / max(sm[x.r], 1e-300)
+        got, want = info.zeta_hist[k + 1], ref.zeta_hist[k + 1]
+        assert abs(got - want) <= allowed * want, (k, got, want, allowed)
+
+
+def test_shipped_network_beats_the_paper_schedule_on_held_out_instances():
+    """On eight held-out instances of the learned-threshold pool (2000 x 2000,
+    r in 5..10, alpha in [0.05, 0.3], c in [0.5, 2]; indices 512-519, never
+    trained on), the shipped network needs fewer iterations on average than
+    the paper's schedule, and every learned solve meets the recovery bar of
+    Section 3 (||L - L_true||_F / ||L_true||_F <= 1e-4)."""
+    th = _shipped()
+    its_p, its_l = [], []
+    for i in range(512, 520):
+        x = I.config_instance(5, i, keep_L=True)
+        D32 = torch.as_tensor(x.D, dtype=torch.float32, device="cuda")
+        ip, _ = _solve(x, None, D32)
+        il, Ll = _solve(x, th, D32)
+        rec = np.linalg.norm(Ll - x.L) / np.linalg.norm(x.L)
+        say(f"held-out {i}: r={x.r} alpha={x.alpha:.3f} c={x.c:.2f}: paper {ip.iterations}, learned "
+            f"{il.iterations}, recovery {rec:.1e}")
+        assert ip.status == R.RPCA_OK and il.status == R.RPCA_OK
+        assert rec <= 1e-4
+        its_p.append(ip.iterations)
+        its_l.append(il.iterations)
+    say(f"mean iterations: paper {np.mean(its_p):.2f}, learned {np.mean(its_l):.2f}")
+    assert np.mean(its_l) < np.mean(its_p)

@@ -128,7 +128,7 @@ def test_tangent_products_edge_thresholds(dtype):
     assert rel(Y1.cpu().numpy(), D @ Vt) < tol
     Y1, Y2, res = sv.tangent_products(dev(A), dev(B), -1.0, dev(Ut), dev(Vt))
     assert res == 0.0
-    assert rel(Y1.cpu().numpy(), (A @ B.T) @ Vt) < 1e-12 if dtype == torch.float64 else 1e-5
+    assert rel(Y1.cpu().numpy(), (A @ B.T) @ Vt) < (1e-12 if dtype == torch.float64 else 1e-5)
 
 
 # ----------------------------------------------------------------- trim ---

@@ -117,3 +117,93 @@ def test_relaxed_step_tends_to_algorithm_1():
     a = np.abs(D - st.L()).ravel()
     assert np.min(np.abs(a - st.zeta)) > 1e-6 * st.zeta
     assert np.abs(L1 - nxt.L()).max() < 1e-9 * np.abs(nxt.L()).max()
+
+
+# ------------------------------------------- Algorithm 1 with the network ---
+
+def _small_case(seed=77, r=3, tol=1e-9):
+    x = I.gaussian_instance(120, 100, r, 0.1, 1.0, seed=seed, tol=tol)
+    p = O.Params(r=r, beta=x.beta, beta_init=x.beta_init, gamma=x.gamma, mu=x.mu_in, tol=tol)
+    return x, p
+
+
+def _bias_only(b3):
+    th = np.zeros(Lr.N_PARAMS)
+    th[-1] = b3
+    return th
+
+
+def test_learned_solve_without_network_is_algorithm_1():
+    x, p = _small_case()
+    ref = O.solve(x.D, p)
+    for th in (None, Lr.init_theta(4)):          # no network, and the untrained one (o = 0 exactly)
+        got = Lr.learned_solve(x.D, p, th)
+        assert got.iterations == ref.iterations
+        assert got.err_hist == ref.err_hist and got.zeta_hist == ref.zeta_hist
+        assert np.array_equal(got.state.L(), ref.state.L())
+    assert Lr.learned_solve(x.D, p, None).learned_hist == [False] * ref.iterations
+    assert Lr.learned_solve(x.D, p, Lr.init_theta(4)).learned_hist[0]
+
+
+def test_learned_solve_nan_network_falls_back_at_once():
+    x, p = _small_case()
+    th = _bias_only(np.nan)
+    got = Lr.learned_solve(x.D, p, th)
+    ref = O.solve(x.D, p)
+    assert not any(got.learned_hist)
+    assert got.err_hist == ref.err_hist and np.array_equal(got.state.L(), ref.state.L())
+
+
+def test_learned_solve_bias_network_scales_the_threshold_step_by_step():
+    # o = b3 = -2 for every input: each learned threshold is e^-2 times the
+    # paper's (low enough that S_k grows and err_k falls from the first body,
+    # so the latch stays open). Composed from independent bodies of
+    # Algorithm 1 whose threshold is replaced by the scaled one.
+    x, p = _small_case()
+    D = x.D
+    f = np.exp(-2.0)
+    got = Lr.learned_solve(D, p, _bias_only(-2.0), fixed_iters=3)
+    nD = O.frobenius(D)
+    st = O.initialize(D, p, nD)
+    assert got.zeta_hist[0] == st.zeta and got.err_hist[0] == st.err
+    for k in range(3):
+        nxt = O.step(D, st, p, nD)                           # the paper's body from the same state
+        paper = O.next_zeta(p.beta, p.gamma, k, nxt.sigma_M, p.r)
+        assert got.learned_hist[k]
+        assert got.zeta_hist[k + 1] == pytest.approx(f * paper, rel=1e-14)
+        np.testing.assert_allclose(got.sigma_hist[k], nxt.sigma_M, rtol=1e-12)
+        st = O.State(U=nxt.U, sigma=nxt.sigma, V=nxt.V, zeta=f * paper, k=k + 1)
+        L1 = st.L()
+        st.err = O.relative_error(D, L1, O.hard_threshold(D - L1, st.zeta), nD)
+        assert got.err_hist[k + 1] == pytest.approx(st.err, rel=1e-10)
+        assert got.err_hist[k + 1] < got.err_hist[k]      # so the latch stays open
+    assert np.linalg.norm(got.state.L() - st.L()) <= 1e-10 * np.linalg.norm(st.L())
+
+
+def test_learned_solve_plateau_closes_the_latch():
+    # While the thresholds exceed every corrupted entry, S_k stays empty and
+    # err_k does not fall (err_1 = err_0 up to rounding on this instance): a
+    # network that keeps the thresholds that high is used for zeta_1 only.
+    x, p = _small_case()
+    got = Lr.learned_solve(x.D, p, _bias_only(np.log(2.0)))
+    assert got.err_hist[1] >= got.err_hist[0]
+    assert got.learned_hist[0] and not any(got.learned_hist[1:])
+    assert got.converged
+
+
+def test_learned_solve_latch_returns_to_the_paper_schedule():
+    # A threshold e^5 times the paper's absorbs too little into S: err rises,
+    # and from that iterate on every threshold is Algorithm 1's again, and the
+    # solve still reaches the tolerance.
+    x, p = _small_case()
+    got = Lr.learned_solve(x.D, p, _bias_only(60.0))
+    first_rise = next(k for k in range(1, len(got.err_hist)) if got.err_hist[k] >= got.err_hist[k - 1])
+    assert got.learned_hist[:first_rise] == [True] * first_rise
+    assert not any(got.learned_hist[first_rise:])
+    for k in range(first_rise, got.iterations):
+        assert got.zeta_hist[k + 1] == O.next_zeta(p.beta, p.gamma, k, got.sigma_hist[k], p.r)
+    for k in range(first_rise):
+        paper = O.next_zeta(p.beta, p.gamma, k, got.sigma_hist[k], p.r)
+        assert got.zeta_hist[k + 1] == pytest.approx(np.exp(5.0) * paper, rel=1e-14)
+    assert got.converged
+    assert O.recovery_error(got.state.L(), x.L) <= 1e-4
