@@ -163,6 +163,23 @@ int rpca_trim(const rpca_params *p, const rpca_state *st,
 int rpca_step(const void *D, const rpca_params *p, rpca_state *st,
               void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (serving loops with a fixed
+ * memory budget, harnesses that forbid hipMalloc): rpca_step with the
+ * workspace taken from a
+ * buffer of RPCA_NOALLOC_WS_BYTES that the library holds in device memory,
+ * one per GPU, from the first call on that GPU until the process ends. The
+ * result is identical to rpca_step's with a caller workspace. Returns
+ * RPCA_EWORKSPACE when the problem needs a larger workspace than that (see
+ * rpca_workspace_size; 10^4 x 10^4 at r = 5 needs 26 MiB with FP32 D and
+ * 48 MiB with FP64 D). The call allocates nothing and creates no runtime
+ * objects (the profiler of rpca_profile_enable does not see it). Every call
+ * on one GPU uses that GPU's single buffer: calls that overlap in time on the
+ * same GPU (other host threads, or other streams whose work has not finished)
+ * race and must be serialised by the caller; the buffer keeps the last call's
+ * contents, none of which a call depends on. */
+#define RPCA_NOALLOC_WS_BYTES (64u << 20)
+int rpca_step_noalloc(const void *D, const rpca_params *p, rpca_state *st, void *stream);
+
 /* Algorithm 3 then Algorithm 1 until err_k < tol or k = max_iter, one fused
  * pass over D per iteration. err_hist / zeta_hist (host, nullable) receive
  * err_0..err_K and zeta_0..zeta_K, at most hist_cap entries each. Returns

@@ -57,14 +57,17 @@ constexpr int STATUS_SLOTS = 32;
 struct DeviceInfo {
     bool checked = false;
     bool ok = false;
+    int id = 0;
     int cus = 256;
-    HostStatus* status_host = nullptr;   // STATUS_SLOTS slots
+    HostStatus* status_host = nullptr;   // STATUS_SLOTS slots, allocated by the first call that needs one
     HostStatus* status_dev = nullptr;
     uint32_t slots_used = 0;             // bit i: slot i belongs to a call (g_dev_mutex)
+    void* scratch = nullptr;             // this device's copy of `scratch` (rpca_step_noalloc)
 };
 std::mutex g_dev_mutex;
 DeviceInfo g_dev[MAX_DEVICES];
 
+// Device check only: properties of the current device, no allocation.
 int device_info(DeviceInfo** out) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -75,21 +78,31 @@ int device_info(DeviceInfo** out) {
         hipDeviceProp_t prop;
         HIP_TRY(hipGetDeviceProperties(&prop, dev));
         d.checked = true;
+        d.id = dev;
         d.ok = std::string(prop.gcnArchName).find("gfx950") != std::string::npos;
         d.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-        if (d.ok) {
-            void* h = nullptr;
-            HIP_TRY(hipHostMalloc(&h, sizeof(HostStatus) * STATUS_SLOTS, hipHostMallocMapped | hipHostMallocCoherent));
-            memset(h, 0, sizeof(HostStatus) * STATUS_SLOTS);
-            void* dp = nullptr;
-            HIP_TRY(hipHostGetDevicePointer(&dp, h, 0));
-            d.status_host = static_cast<HostStatus*>(h);
-            d.status_dev = static_cast<HostStatus*>(dp);
-        }
     }
     if (!d.ok) return RPCA_ENODEV;
     *out = &d;
     return RPCA_OK;
+}
+
+// The device's status slots in mapped, coherent host memory (g_dev_mutex held).
+bool status_slots_locked(DeviceInfo* d) {
+    if (d->status_host) return true;
+    void* h = nullptr;
+    if (hipHostMalloc(&h, sizeof(HostStatus) * STATUS_SLOTS, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+        return false;
+    memset(h, 0, sizeof(HostStatus) * STATUS_SLOTS);
+    void* dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, h, 0) != hipSuccess) {
+        (void)hipHostFree(h);
+        return false;
+    }
+    d->status_host = static_cast<HostStatus*>(h);
+    d->status_dev = static_cast<HostStatus*>(dp);
+    return true;
 }
 
 // A status slot held for the duration of one call.
@@ -97,6 +110,7 @@ class StatusSlot {
 public:
     explicit StatusSlot(DeviceInfo* d) : d_(d) {
         std::lock_guard<std::mutex> lock(g_dev_mutex);
+        if (!status_slots_locked(d_)) return;
         for (int i = 0; i < STATUS_SLOTS; ++i) {
             if (!(d_->slots_used & (1u << i))) {
                 d_->slots_used |= 1u << i;
@@ -175,7 +189,13 @@ int prof_collect_locked() {
 
 // Launch of the streaming pass (mx: products on the matrix cores in BF16),
 // bracketed by events when profiling is on.
-int stream_launch(const StreamArgs& a, int K, int dtype, bool rebuild, bool mx, hipStream_t s) {
+// events = false: never (rpca_step_noalloc, which creates no runtime objects).
+int stream_launch(const StreamArgs& a, int K, int dtype, bool rebuild, bool mx, hipStream_t s, bool events = true) {
+    if (!events) {
+        if (mx) HIP_TRY(launch_stream_mx(a, K, rebuild, s));
+        else HIP_TRY(launch_stream(a, K, dtype, rebuild, s));
+        return RPCA_OK;
+    }
     std::lock_guard<std::mutex> lock(g_prof.mu);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (g_prof.on) {
@@ -337,6 +357,7 @@ struct Ctx {
     double mixed_err;
     HostStatus* st_host = nullptr;   // the call's status slot (queues of bodies only)
     HostStatus* st_dev = nullptr;
+    bool events = true;              // false: no profiler events (rpca_step_noalloc)
     Ctrl* ctrl() const { return reinterpret_cast<Ctrl*>(ws + L.off_ctrl); }
     Small* small() const { return reinterpret_cast<Small*>(ws + L.off_small); }
     double* err_hist() const { return reinterpret_cast<double*>(ws + L.off_hist); }
@@ -479,7 +500,7 @@ int enqueue_body(const Ctx& c, const void* D, int K, int body, double* state_U, 
     const bool fp32 = c.dtype == RPCA_F32;
     const Geo g = geo_for(c, K, rebuild, mx);
     StreamArgs sa = stream_args(c, D, body, g);
-    RPCA_TRY(stream_launch(sa, K, c.dtype, rebuild, mx, c.s));
+    RPCA_TRY(stream_launch(sa, K, c.dtype, rebuild, mx, c.s, c.events));
     PanelArgs pa = panel_args(c, g);
     pa.body = body;
     pa.lcorr = rebuild ? 1 : 0;
@@ -619,7 +640,7 @@ int run_init(const Ctx& c, const void* D, rpca_state* st, Ctrl* ctrl_out) {
 int threshold_pass(const Ctx& c, const void* D, bool rebuild) {
     const int K = c.p->r;
     const Geo g = geo_for(c, K, rebuild);
-    RPCA_TRY(stream_launch(stream_args(c, D, BODY_ANY, g), K, c.dtype, rebuild, false, c.s));
+    RPCA_TRY(stream_launch(stream_args(c, D, BODY_ANY, g), K, c.dtype, rebuild, false, c.s, c.events));
     PanelArgs pa = panel_args(c, g);
     pa.lcorr = rebuild ? 1 : 0;
     HIP_TRY(launch_gather(pa, K, c.dtype, c.s));
@@ -641,11 +662,34 @@ int check_state(const rpca_state* st) {
     return RPCA_OK;
 }
 
+// Workspace of rpca_step_noalloc: a fixed array in device memory, one copy
+// per GPU (the runtime provides it when the library's code is loaded on that
+// device, and it stays until the process ends). Host code never passes the
+// array's name to a kernel: it is a host-side stand-in for the symbol, not a
+// device address. The device address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and is kept in DeviceInfo.
+static __device__ __align__(256) unsigned char scratch[RPCA_NOALLOC_WS_BYTES];
+
+int noalloc_workspace(DeviceInfo* d, void** out) {
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    if (!d->scratch) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr || ((uintptr_t)ptr & 255u) != 0) {
+            g_last_hip_error = (int)(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            return RPCA_EHIP;
+        }
+        d->scratch = ptr;
+    }
+    *out = d->scratch;
+    return RPCA_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int rpca_version(void) { return 100; }
+int rpca_version(void) { return 101; }
 
 int rpca_profile_enable(int on) {
     std::lock_guard<std::mutex> lock(g_prof.mu);
@@ -996,12 +1040,15 @@ int compute_normD2(const Ctx& c, const void* D, double* out) {
 }
 }  // namespace
 
-int rpca_step(const void* D, const rpca_params* p, rpca_state* st, void* ws, size_t ws_bytes, void* stream) {
+namespace {
+int step_impl(const void* D, const rpca_params* p, rpca_state* st, void* ws, size_t ws_bytes, void* stream,
+              bool events) {
     if (!D) return RPCA_EINVAL;
     RPCA_TRY(check_state(st));
     if (!is_fin(st->zeta) || st->k < 0) return RPCA_EINVAL;
     Ctx c;
     RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
+    c.events = events;
     double nd2 = st->normD > 0 ? st->normD * st->normD : 0.0;
     if (!(nd2 > 0)) RPCA_TRY(compute_normD2(c, D, &nd2));
     RPCA_TRY(setup(c, base_ctrl(c, STAGE_MAIN, st->zeta, st->k, nd2, 0)));
@@ -1020,6 +1067,21 @@ int rpca_step(const void* D, const rpca_params* p, rpca_state* st, void* ws, siz
     if (t.nonfinite) return RPCA_EINVAL;
     fill_state(st, t);
     return RPCA_OK;
+}
+}  // namespace
+
+int rpca_step(const void* D, const rpca_params* p, rpca_state* st, void* ws, size_t ws_bytes, void* stream) {
+    return step_impl(D, p, st, ws, ws_bytes, stream, true);
+}
+
+int rpca_step_noalloc(const void* D, const rpca_params* p, rpca_state* st, void* stream) {
+    RPCA_TRY(validate(p));
+    if (make_layout(p).total > RPCA_NOALLOC_WS_BYTES) return RPCA_EWORKSPACE;
+    DeviceInfo* dev = nullptr;
+    RPCA_TRY(device_info(&dev));
+    void* ws = nullptr;
+    RPCA_TRY(noalloc_workspace(dev, &ws));
+    return step_impl(D, p, st, ws, RPCA_NOALLOC_WS_BYTES, stream, false);
 }
 
 int rpca_relaxed_step(const void* D, const rpca_params* p, rpca_state* st, double zeta, double tau,

@@ -34,7 +34,8 @@ RPCA_MLP_PARAMS = 1249
 RPCA_PROF_KINDS = 3
 RPCA_MAX_RANK = 16
 
-EXPORTED = ("rpca_workspace_size", "rpca_init", "rpca_trim", "rpca_step", "rpca_solve", "rpca_solve_many",
+EXPORTED = ("rpca_workspace_size", "rpca_init", "rpca_trim", "rpca_step", "rpca_step_noalloc", "rpca_solve",
+            "rpca_solve_many",
             "rpca_materialize", "rpca_tangent_products", "rpca_strerror",
             "rpca_last_hip_error", "rpca_version", "rpca_profile_enable", "rpca_profile_read",
             "rpca_relaxed_step", "rpca_mlp_forward", "rpca_mlp_backward", "rpca_mlp_adam")
@@ -90,6 +91,7 @@ def _lib():
             "rpca_init": [vp, P, S, vp, sz, vp],
             "rpca_trim": [P, S, vp, vp, vp, sz, vp],
             "rpca_step": [vp, P, S, vp, sz, vp],
+            "rpca_step_noalloc": [vp, P, S, vp],
             "rpca_solve": [vp, P, S, pd, pd, ctypes.c_int32, vp, sz, vp],
             "rpca_solve_many": [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(P), ctypes.POINTER(S),
                                 ctypes.POINTER(pd), ctypes.POINTER(pd), ctypes.c_int32, ctypes.POINTER(vp),
@@ -166,6 +168,15 @@ def rpca_step(D, params, state, ws, stream=None) -> int:
     w, nb = _ws(ws)
     return _check(_lib().rpca_step(_ptr(D), ctypes.byref(params), ctypes.byref(state), w, nb, _stream(stream)),
                   "rpca_step")
+
+
+RPCA_NOALLOC_WS_BYTES = 64 << 20
+
+
+def rpca_step_noalloc(D, params, state, stream=None) -> int:
+    """rpca_step with the library's own per-GPU workspace (allocates nothing)."""
+    return _check(_lib().rpca_step_noalloc(_ptr(D), ctypes.byref(params), ctypes.byref(state), _stream(stream)),
+                  "rpca_step_noalloc")
 
 
 def rpca_relaxed_step(D, params, state, zeta, tau, P, Q, ws, stream=None) -> RelaxResult:
@@ -370,6 +381,9 @@ class Solver:
 
     def step(self) -> None:
         rpca_step(self.D, self.params, self.state, self.ws)
+
+    def step_noalloc(self) -> None:
+        rpca_step_noalloc(self.D, self.params, self.state)
 
     def trim(self):
         m, n = self.D.shape
