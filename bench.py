@@ -10,17 +10,21 @@ schedule (plain), the mixed-precision passes, the learned threshold schedule
 (shipped network) and both; value is the learned form.
 
 Printed JSON line:
-  value        seconds to err <= 1e-5 per solve (mean over the timed steps),
-               learned threshold schedule; the other forms under config.forms
+  value        seconds to err <= 1e-5 per solve (median of the timed steps,
+               each a synchronised solve), learned threshold schedule; the
+               other forms under config.forms
   roofline     the loop's streaming pass over D (the dominant kernel,
                k_stream<float, r, rebuild>): algorithmic bytes per launch =
                4 bytes x m x n (D read once, FP32) divided by its mean
                duration, measured with HIP events on the launch stream over a
-               second timed region of the headline form
+               second timed region of the headline form. config also carries
+               the same bytes over a whole loop body (one iteration: pass,
+               gather, update; "per step"), and the bandwidth of a plain read
+               of D (rpca_read_probe) as the achievable reference
   cpu_baseline the FP64 CPU oracle on this host (paper schedule) on the same
                instance: the initialisation plus as many iterations as the
                GPU needed with the paper's schedule (--cpu-iters N times N
-               of them and extrapolates)
+               of them and extrapolates); the CPU model is named in `sample`
 """
 from __future__ import annotations
 
@@ -77,6 +81,18 @@ def log(args, *a):
         print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown CPU"
+
+
 def cpu_baseline(x, gpu_iters: int, n_iters: int):
     """Oracle on the host: init + n_iters bodies (0: gpu_iters), extrapolated to gpu_iters."""
     import numpy as np
@@ -98,18 +114,21 @@ def cpu_baseline(x, gpu_iters: int, n_iters: int):
         st = O.step(D, st, p, normD)
     t_iter = (time.perf_counter() - t1) / max(1, n_iters)
     est = t_init + gpu_iters * t_iter
+    host = f"{cpu_model()}, {threads} threads"
     if n_iters == gpu_iters:
-        sample = (f"FP64 numpy/scipy oracle on this host, the whole solve of the same instance: initialisation "
-                  f"({t_init:.2f} s) plus the {n_iters} iterations of the paper's schedule ({t_iter:.2f} s each)")
+        sample = (f"FP64 numpy/scipy oracle on this host ({host}), the whole solve of the same instance: "
+                  f"initialisation ({t_init:.2f} s) plus the {n_iters} iterations of the paper's schedule "
+                  f"({t_iter:.2f} s each)")
     else:
-        sample = (f"FP64 numpy/scipy oracle on this host: initialisation ({t_init:.2f} s) plus {n_iters} "
+        sample = (f"FP64 numpy/scipy oracle on this host ({host}): initialisation ({t_init:.2f} s) plus {n_iters} "
                   f"iterations ({t_iter:.2f} s each) of the same instance, extrapolated to the "
                   f"{gpu_iters} iterations the GPU needed")
     return {"value": round(est, 3), "unit": "s", "cores": int(threads), "kind": "oracle", "sample": sample}
 
 
 def run_leg(R, torch, x, D, args, log_name, **kw):
-    """Warmup + timed solves of one form; returns (seconds per solve, info, solver)."""
+    """Warmup + timed solves of one form; returns (median and mean seconds per
+    solve, info, solver). Each solve returns after its stream has drained."""
     sv = R.Solver(D, x.r, x.beta, x.beta_init, x.gamma, x.mu_in, tol=x.tol, max_iter=100, seed=1,
                   init_block=args.init_block, **kw)
     for i in range(args.warmup):
@@ -117,11 +136,15 @@ def run_leg(R, torch, x, D, args, log_name, **kw):
         log(args, f"{log_name} warmup {i}: iterations {info.iterations} init passes {info.init_passes} "
                   f"err {info.err:.3e}")
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    ts = []
     for _ in range(args.steps):
+        t0 = time.perf_counter()
         info = sv.solve()
+        ts.append(time.perf_counter() - t0)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / args.steps, info, sv
+    ts.sort()
+    med = ts[len(ts) // 2] if len(ts) % 2 else 0.5 * (ts[len(ts) // 2 - 1] + ts[len(ts) // 2])
+    return med, sum(ts) / len(ts), info, sv
 
 
 def recovery(torch, sv, x, dev):
@@ -167,11 +190,11 @@ def main():
     forms = {k: v for k, v in forms.items() if k in want}
     res = {}
     for name, kw in forms.items():
-        per, info, sv = run_leg(R, torch, x, D, args, name, **kw)
-        res[name] = {"s": per, "iterations": info.iterations, "init_passes": info.init_passes,
+        per, mean, info, sv = run_leg(R, torch, x, D, args, name, **kw)
+        res[name] = {"s": per, "s_mean": mean, "iterations": info.iterations, "init_passes": info.init_passes,
                      "final_err": info.err, "recovery_rel_err": recovery(torch, sv, x, dev), "solver": sv}
-        log(args, f"{name}: {per * 1e3:.3f} ms per solve, {info.iterations} iterations, "
-                  f"recovery {res[name]['recovery_rel_err']:.2e}")
+        log(args, f"{name}: {per * 1e3:.3f} ms per solve (median; mean {mean * 1e3:.3f}), {info.iterations} "
+                  f"iterations, recovery {res[name]['recovery_rel_err']:.2e}")
     head = "learned"
     info_head = res[head]
 
@@ -186,16 +209,32 @@ def main():
     torch.cuda.synchronize()
     t_prof = time.perf_counter() - t1
     R.rpca_profile_enable(False)
-    (ms_stream, n_stream), _, (ms_init, n_init) = R.rpca_profile_read_all()
+    (ms_stream, n_stream), _, (ms_init, n_init), (ms_body, n_body) = R.rpca_profile_read_all()
+
+    # achievable read bandwidth: a plain read of the same D (rpca_read_probe)
+    sink = torch.empty((R.RPCA_PROBE_SINK,), dtype=torch.float32, device=dev)
+    for _ in range(3):
+        R.rpca_read_probe(D, sink)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        R.rpca_read_probe(D, sink)
+    e1.record()
+    e1.synchronize()
+    probe_us = e0.elapsed_time(e1) * 1e3 / 20
+    bytes_per_pass = 4.0 * m * n
+    probe_gbps = bytes_per_pass / (probe_us * 1e-6) / 1e9
 
     per_solve = info_head["s"]
     passes_per_solve = (n_stream + n_init) / args.steps
     avg_pass_ms = ms_stream / max(1, n_stream)          # the loop's pass: the dominant kernel
     avg_init_ms = ms_init / max(1, n_init)
-    bytes_per_pass = 4.0 * m * n
+    avg_body_ms = ms_body / max(1, n_body)              # one iteration: pass, gather, update
     achieved = bytes_per_pass / (avg_pass_ms * 1e-3) / 1e9
+    body_gbps = bytes_per_pass / (avg_body_ms * 1e-3) / 1e9
     log(args, f"headline ({head}): {per_solve * 1e3:.3f} ms per solve, {passes_per_solve:.1f} passes, "
-              f"stream pass {avg_pass_ms * 1e3:.1f} us -> {achieved:.0f} GB/s")
+              f"stream pass {avg_pass_ms * 1e3:.1f} us -> {achieved:.0f} GB/s; loop body {avg_body_ms * 1e3:.1f} us "
+              f"-> {body_gbps:.0f} GB/s; plain read of D {probe_us:.1f} us -> {probe_gbps:.0f} GB/s")
 
     out = {
         "metric": METRIC,
@@ -224,6 +263,13 @@ def main():
             "init_pass_us": round(avg_init_ms * 1e3, 2),
             "init_pass_GBps": round(bytes_per_pass / (avg_init_ms * 1e-3) / 1e9, 1) if n_init else None,
             "ms_per_step_with_events": round(t_prof / args.steps * 1e3, 4),
+            "ms_per_step_mean": round(info_head["s_mean"] * 1e3, 4),
+            "loop_body_us": round(avg_body_ms * 1e3, 2),
+            "loop_body_GBps": round(body_gbps, 1),
+            "loop_body_frac": round(body_gbps / HBM_PEAK_GBPS, 4),
+            "read_probe_us": round(probe_us, 2),
+            "read_probe_GBps": round(probe_gbps, 1),
+            "stream_pass_frac_of_read_probe": round(achieved / probe_gbps, 4),
             "forms": {k: {"s": round(v["s"], 6), "iterations": v["iterations"],
                           "recovery_rel_err": v["recovery_rel_err"]} for k, v in res.items()},
             "speedup_vs_plain": round(res["plain"]["s"] / per_solve, 3) if "plain" in res else None,

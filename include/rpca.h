@@ -275,12 +275,23 @@ int rpca_mlp_adam(float *theta, float *m, float *v, const float *grad, int32_t t
  * duration in ms and their number since the previous read, then resets them:
  * stream_ms and stream_launches are arrays of RPCA_PROF_KINDS entries: [0] the
  * loop's passes in the dtype of D, [1] the loop's passes with the BF16
- * product, [2] the passes of the initialisation (L = 0). Disabling keeps
- * the totals for a final read. Intended for benchmarks: the events add a few
- * microseconds of queue work per pass. */
-#define RPCA_PROF_KINDS 3
+ * product, [2] the passes of the initialisation (L = 0), [3] whole loop
+ * bodies of rpca_solve (from before the pass to the end of the body's last
+ * kernel: one iteration of Algorithm 1). Disabling keeps the totals for a
+ * final read. Intended for benchmarks: the events add a few microseconds of
+ * queue work per pass. */
+#define RPCA_PROF_KINDS 4
 int rpca_profile_enable(int on);
 int rpca_profile_read(double *stream_ms, int64_t *stream_launches);
+
+/* Reference for the streaming pass's bandwidth: one launch on `stream` that
+ * reads the `bytes` bytes at `data` (device, 16-byte aligned, bytes a positive
+ * multiple of 16) once with 16-byte loads and no arithmetic to speak of;
+ * `sink` is device scratch of RPCA_PROBE_SINK floats (not meaningfully
+ * written). Timing it around the launch gives the read bandwidth the device
+ * reaches on the same data. */
+#define RPCA_PROBE_SINK 8192
+int rpca_read_probe(const void *data, int64_t bytes, float *sink, void *stream);
 
 /* Static description of a status code. */
 const char *rpca_strerror(int status);

@@ -155,10 +155,11 @@ struct Profiler {
     struct Rec {
         hipEvent_t e0, e1;
         int kind;
+        int32_t body;   // id of the queued body the record belongs to (0: none)
     };
     std::vector<Rec> pending;
-    double ms[RPCA_PROF_KINDS] = {0.0, 0.0, 0.0};
-    int64_t launches[RPCA_PROF_KINDS] = {0, 0, 0};
+    double ms[RPCA_PROF_KINDS] = {0.0, 0.0, 0.0, 0.0};
+    int64_t launches[RPCA_PROF_KINDS] = {0, 0, 0, 0};
 };
 Profiler g_prof;
 
@@ -190,7 +191,8 @@ int prof_collect_locked() {
 // Launch of the streaming pass (mx: products on the matrix cores in BF16),
 // bracketed by events when profiling is on.
 // events = false: never (rpca_step_noalloc, which creates no runtime objects).
-int stream_launch(const StreamArgs& a, int K, int dtype, bool rebuild, bool mx, hipStream_t s, bool events = true) {
+int stream_launch(const StreamArgs& a, int K, int dtype, bool rebuild, bool mx, hipStream_t s, bool events = true,
+                  int32_t body_id = 0) {
     if (!events) {
         if (mx) HIP_TRY(launch_stream_mx(a, K, rebuild, s));
         else HIP_TRY(launch_stream(a, K, dtype, rebuild, s));
@@ -209,21 +211,45 @@ int stream_launch(const StreamArgs& a, int K, int dtype, bool rebuild, bool mx, 
     else HIP_TRY(launch_stream(a, K, dtype, rebuild, s));
     if (g_prof.on) {
         HIP_TRY(hipEventRecord(e1, s));
-        g_prof.pending.push_back({e0, e1, mx ? 1 : (rebuild ? 0 : 2)});
+        g_prof.pending.push_back({e0, e1, mx ? 1 : (rebuild ? 0 : 2), body_id});
     }
     return RPCA_OK;
 }
 
-// The last queued body of a loop ran past the stop and did no work: drop its pass.
+// Event before a loop body (profiling on): the pair is closed by prof_body_end.
+int prof_body_begin(hipStream_t s, hipEvent_t* e0) {
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    *e0 = nullptr;
+    if (!g_prof.on) return RPCA_OK;
+    if (g_prof.pending.size() >= 4096) RPCA_TRY(prof_collect_locked());
+    *e0 = prof_event();
+    if (!*e0) return RPCA_EHIP;
+    HIP_TRY(hipEventRecord(*e0, s));
+    return RPCA_OK;
+}
+int prof_body_end(hipStream_t s, hipEvent_t e0, int32_t body_id) {
+    if (!e0) return RPCA_OK;
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    hipEvent_t e1 = prof_event();
+    if (!e1) return RPCA_EHIP;
+    HIP_TRY(hipEventRecord(e1, s));
+    g_prof.pending.push_back({e0, e1, 3, body_id});
+    return RPCA_OK;
+}
+
+// The last queued body of a loop ran past the stop and did no work: drop its
+// records (its pass and, for a loop body, the body itself).
 void prof_drop_last() {
     std::lock_guard<std::mutex> lock(g_prof.mu);
-    if (g_prof.on && !g_prof.pending.empty()) {
+    if (!g_prof.on || g_prof.pending.empty()) return;
+    const int32_t body = g_prof.pending.back().body;
+    do {
         auto pr = g_prof.pending.back();
         g_prof.pending.pop_back();
         (void)hipEventSynchronize(pr.e1);
         g_prof.pool.push_back(pr.e0);
         g_prof.pool.push_back(pr.e1);
-    }
+    } while (body != 0 && !g_prof.pending.empty() && g_prof.pending.back().body == body);
 }
 
 int init_block_of(const rpca_params* p) {
@@ -500,7 +526,9 @@ int enqueue_body(const Ctx& c, const void* D, int K, int body, double* state_U, 
     const bool fp32 = c.dtype == RPCA_F32;
     const Geo g = geo_for(c, K, rebuild, mx);
     StreamArgs sa = stream_args(c, D, body, g);
-    RPCA_TRY(stream_launch(sa, K, c.dtype, rebuild, mx, c.s, c.events));
+    hipEvent_t eb = nullptr;
+    if (body == BODY_MAIN && c.events) RPCA_TRY(prof_body_begin(c.s, &eb));
+    RPCA_TRY(stream_launch(sa, K, c.dtype, rebuild, mx, c.s, c.events, body_id));
     PanelArgs pa = panel_args(c, g);
     pa.body = body;
     pa.lcorr = rebuild ? 1 : 0;
@@ -526,6 +554,7 @@ int enqueue_body(const Ctx& c, const void* D, int K, int body, double* state_U, 
         ua.sigma_dst = state_sigma;
     }
     HIP_TRY(launch_update(ua, K, c.dtype, c.s));
+    RPCA_TRY(prof_body_end(c.s, eb, body_id));
     return RPCA_OK;
 }
 
@@ -712,6 +741,16 @@ int rpca_profile_read(double* stream_ms, int64_t* stream_launches) {
 }
 
 int rpca_last_hip_error(void) { return g_last_hip_error; }
+
+int rpca_read_probe(const void* data, int64_t bytes, float* sink, void* stream) {
+    if (!data || !sink || bytes <= 0 || (bytes & 15) != 0 || ((uintptr_t)data & 15u) != 0) return RPCA_EINVAL;
+    DeviceInfo* dev = nullptr;
+    RPCA_TRY(device_info(&dev));
+    int blocks = 8 * dev->cus;
+    if (blocks > RPCA_PROBE_SINK) blocks = RPCA_PROBE_SINK;
+    HIP_TRY(launch_read_probe(data, bytes, sink, blocks, static_cast<hipStream_t>(stream)));
+    return RPCA_OK;
+}
 
 const char* rpca_strerror(int status) {
     switch (status) {

@@ -118,6 +118,7 @@ int stream_mx_occupancy(int K, bool rebuild);
 hipError_t launch_stream_mx(const StreamArgs& a, int K, bool rebuild, hipStream_t s);
 hipError_t launch_stream(const StreamArgs& a, int K, int dtype, bool rebuild, hipStream_t s);
 hipError_t launch_materialize(const MaterializeArgs& a, int K, int dtype, hipStream_t s);
+hipError_t launch_read_probe(const void* data, int64_t bytes, float* sink, int blocks, hipStream_t s);
 hipError_t launch_gather(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_complement(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_update(const PanelArgs& a, int K, int dtype, hipStream_t s);

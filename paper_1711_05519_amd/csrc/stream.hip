@@ -377,6 +377,26 @@ __global__ __launch_bounds__(256) void k_materialize(MaterializeArgs a) {
     }
 }
 
+// Read-bandwidth reference: every 16-byte word of [p, p + n16) read once,
+// eight loads in flight per thread, no arithmetic beyond a sum that is
+// written only if it equals an impossible value (so the loads stay).
+__global__ __launch_bounds__(256) void k_read_probe(const float4* __restrict__ p, int64_t n16, float* sink) {
+    constexpr int U = 8;
+    float acc = 0.f;
+    const int64_t stride = (int64_t)gridDim.x * 256 * U;
+    for (int64_t i = (int64_t)blockIdx.x * 256 * U + threadIdx.x; i < n16; i += stride) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = i + (int64_t)u * 256;
+            v[u] = j < n16 ? p[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+    }
+    if (acc == -1.2345e-38f) sink[blockIdx.x] = acc;
+}
+
 template <typename T, bool REBUILD>
 hipError_t stream_dispatch(const StreamArgs& a, int K, hipStream_t s) {
     using Acc = typename AccOf<T>::type;
@@ -449,6 +469,12 @@ int stream_occupancy(int K, int dtype, bool rebuild) {
 hipError_t launch_stream(const StreamArgs& a, int K, int dtype, bool rebuild, hipStream_t s) {
     if (dtype == 1) return rebuild ? stream_dispatch<float, true>(a, K, s) : stream_dispatch<float, false>(a, K, s);
     return rebuild ? stream_dispatch<double, true>(a, K, s) : stream_dispatch<double, false>(a, K, s);
+}
+
+hipError_t launch_read_probe(const void* data, int64_t bytes, float* sink, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_read_probe, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const float4*>(data),
+                       bytes / 16, sink);
+    return hipGetLastError();
 }
 
 hipError_t launch_materialize(const MaterializeArgs& a, int K, int dtype, hipStream_t s) {

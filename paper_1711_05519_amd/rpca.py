@@ -31,14 +31,14 @@ RPCA_FLAG_MIXED = 2
 RPCA_FLAG_TRAINING = 4
 RPCA_FLAG_LEARNED = 8
 RPCA_MLP_PARAMS = 1249
-RPCA_PROF_KINDS = 3
+RPCA_PROF_KINDS = 4
 RPCA_MAX_RANK = 16
 
 EXPORTED = ("rpca_workspace_size", "rpca_init", "rpca_trim", "rpca_step", "rpca_step_noalloc", "rpca_solve",
             "rpca_solve_many",
             "rpca_materialize", "rpca_tangent_products", "rpca_strerror",
             "rpca_last_hip_error", "rpca_version", "rpca_profile_enable", "rpca_profile_read",
-            "rpca_relaxed_step", "rpca_mlp_forward", "rpca_mlp_backward", "rpca_mlp_adam")
+            "rpca_relaxed_step", "rpca_mlp_forward", "rpca_mlp_backward", "rpca_mlp_adam", "rpca_read_probe")
 
 
 class RpcaError(RuntimeError):
@@ -100,6 +100,7 @@ def _lib():
             "rpca_tangent_products": [vp, P, vp, vp, d, vp, vp, vp, vp, pd, vp, sz, vp],
             "rpca_relaxed_step": [vp, P, S, d, d, vp, vp, ctypes.c_int32, ctypes.POINTER(RelaxResult), vp, sz, vp],
             "rpca_mlp_forward": [vp, vp, ctypes.c_int32, vp, vp],
+            "rpca_read_probe": [vp, ctypes.c_int64, vp, vp],
             "rpca_mlp_backward": [vp, vp, vp, ctypes.c_int32, vp, vp],
             "rpca_mlp_adam": [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, vp],
@@ -277,6 +278,19 @@ def rpca_tangent_products(D, params, A_L, B_L, zeta, U_t, V_t, Y1, Y2, ws, strea
     return float(out.value)
 
 
+RPCA_PROBE_SINK = 8192
+
+
+def rpca_read_probe(data: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
+    """One read of every byte of `data` (a contiguous device tensor) with no
+    arithmetic: the bandwidth reference of the streaming pass."""
+    if not data.is_contiguous() or sink.dtype != torch.float32 or sink.numel() < RPCA_PROBE_SINK:
+        raise ValueError("contiguous data and a float32 sink of RPCA_PROBE_SINK values are required")
+    nbytes = data.numel() * data.element_size()
+    _check(_lib().rpca_read_probe(_ptr(data), nbytes - nbytes % 16, _ptr(sink), _stream(stream)),
+           "rpca_read_probe")
+
+
 def rpca_profile_enable(on: bool) -> None:
     _check(_lib().rpca_profile_enable(1 if on else 0), "rpca_profile_enable")
 
@@ -294,8 +308,8 @@ def rpca_profile_read(kind: int | None = None):
 
 
 def rpca_profile_read_all():
-    """[(ms, count)] of the loop's dtype passes, its BF16-product passes and the
-    initialisation's passes."""
+    """[(ms, count)] of the loop's dtype passes, its BF16-product passes, the
+    initialisation's passes and whole loop bodies."""
     ms = (ctypes.c_double * RPCA_PROF_KINDS)()
     n = (ctypes.c_int64 * RPCA_PROF_KINDS)()
     _check(_lib().rpca_profile_read(ms, n), "rpca_profile_read")
