@@ -66,13 +66,14 @@ extern "C" {
 
 /* ---- flags ------------------------------------------------------------- */
 #define RPCA_FLAG_NO_TRIM 1u  /* AccAltProj without trim (Section 3): U~ = U_k, V~ = V_k */
-/* Mixed-precision form (RPCA_F32 only): of the tangent product
- * Y1 = (D - S_k) V~ = L_k V~ + E V~ (E = D - L_k - S_k, the residual part), the
- * product E V~ of a loop body runs on the matrix cores with BF16 operands and
- * FP32 accumulation, and L_k V~ is added exactly from the factors; so the
- * BF16 rounding error of Y1 is about 2^-8 err_k relative and falls with err_k.
- * Y2 = (D - S_k)^T U~, the rebuild of L_k, the threshold, the residual and
- * err_k stay FP32, as does all small algebra (FP64). By default every loop
+/* Mixed-precision form (RPCA_F32 only): of the tangent products
+ * Y1 = (D - S_k) V~ = L_k V~ + E V~ and Y2 = (D - S_k)^T U~ = L_k^T U~ + E^T U~
+ * (E = D - L_k - S_k, the residual part), the products E V~ and E^T U~ of a
+ * loop body run on the matrix cores with BF16 operands and FP32
+ * accumulation, and the rank-r parts are added exactly from the factors; so
+ * the BF16 rounding error of Y1 and Y2 is about 2^-8 err_k relative and falls
+ * with err_k. The rebuild of L_k, the threshold, the residual and err_k stay
+ * FP32, as does all small algebra (FP64). By default every loop
  * body takes BF16 products. With mixed_err > 0, body k of rpca_solve (which
  * computes err_k and L_{k+1}) takes them while err_j >= mixed_err for every
  * j <= k - 2 (bodies 0 and 1 always do: the host decides one body ahead) and

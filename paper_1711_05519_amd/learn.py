@@ -117,7 +117,30 @@ def unroll(pb: Problem, theta: torch.Tensor | None, steps: int, tau_rel: float):
     return losses, phis, gos
 
 
-VALIDATION_IDS = (500, 501, 502, 503)   # training pool instances held out of the training set
+VALIDATION_IDS = (500, 501, 502, 503)   # training pool instances held out of the training set (small runs)
+POOL = 512                              # instances 0 .. 511 form the training pool, 512 .. 575 the test set
+
+
+def split(n_instances: int):
+    """Gradient instances and validation instances of a run on the first
+    n_instances of the pool: runs on the whole pool keep its last 32 for
+    choosing the epoch; smaller runs validate on VALIDATION_IDS."""
+    if n_instances >= 256:
+        return list(range(n_instances - 32)), tuple(range(n_instances - 32, n_instances))
+    return list(range(n_instances)), VALIDATION_IDS
+
+
+_SOLVE_CACHE: dict = {}   # (instance, dtype) -> (instance without D, D on the device)
+
+
+def _instance_on_device(i: int, dtype):
+    key = (i, dtype)
+    if key not in _SOLVE_CACHE:
+        x = I.config_instance(5, i, keep_L=False)
+        D = torch.as_tensor(x.D, dtype=dtype, device="cuda")
+        x.D = None
+        _SOLVE_CACHE[key] = (x, D)
+    return _SOLVE_CACHE[key]
 
 
 def solve_stats(theta, ids, dtype=torch.float32):
@@ -125,8 +148,7 @@ def solve_stats(theta, ids, dtype=torch.float32):
     error ||L - L_true||_F / ||L_true||_F, all converged)."""
     its, worst, ok = [], 0.0, True
     for i in ids:
-        x = I.config_instance(5, i)
-        D = torch.as_tensor(x.D, dtype=dtype, device="cuda")
+        x, D = _instance_on_device(i, dtype)
         sv = R.Solver(D, x.r, x.beta, x.beta_init, x.gamma, x.mu_in, tol=x.tol, seed=1, learned=theta)
         info = sv.solve()
         U, s_, V = sv.L_factors()
@@ -149,18 +171,27 @@ def solve_stats(theta, ids, dtype=torch.float32):
 def train(n_instances: int = 32, epochs: int = 12, steps: int = 15, tau0: float = 0.2, lr: float = 3e-4,
           seed: int = 0, dtype=torch.float64, log=print):
     """Trains the network on the first n_instances of the training pool
-    (inputs.config_instance(5, i)). After every epoch the network solves the
-    validation instances to tol with the hard threshold; the returned theta is
-    the epoch with the fewest mean iterations among those whose solves all
-    converge with recovery error <= 1e-4 (the untrained network, i.e. the
-    paper's schedule, if none). Returns (theta, history)."""
+    (inputs.config_instance(5, i)), split into gradient and validation
+    instances (split()). After every epoch the network solves the validation
+    instances to tol with the hard threshold; the returned theta is the epoch
+    with the fewest mean iterations among those whose solves all converge with
+    recovery error <= 1e-4 (the untrained network, i.e. the paper's schedule,
+    if none). Returns (theta, history)."""
     dev = torch.device("cuda")
     t0 = time.perf_counter()
-    problems = [make_problem(I.config_instance(5, i), dtype, dev) for i in range(n_instances)]
-    log(f"{n_instances} training instances ready in {time.perf_counter() - t0:.1f} s")
+    train_ids, val_ids = split(n_instances)
+    problems = []
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:   # instance draws on the host, in parallel
+        for x in ex.map(lambda i: I.config_instance(5, i, keep_L=False), train_ids):
+            problems.append(make_problem(x, dtype, dev))
+            if len(problems) % 64 == 0:
+                log(f"{len(problems)} of {len(train_ids)} training instances ready ({time.perf_counter() - t0:.1f} s)")
+    log(f"{len(train_ids)} training instances ready in {time.perf_counter() - t0:.1f} s; "
+        f"validation on {len(val_ids)} instances")
     theta = init_theta(seed, dev)
     best = theta.clone()
-    best_its, _, _ = solve_stats(None, VALIDATION_IDS)
+    best_its, _, _ = solve_stats(None, val_ids)
     log(f"paper schedule: {best_its:.2f} mean iterations on the validation instances")
     m = torch.zeros_like(theta)
     v = torch.zeros_like(theta)
@@ -181,7 +212,7 @@ def train(n_instances: int = 32, epochs: int = 12, steps: int = 15, tau0: float 
             t += 1
             R.rpca_mlp_adam(theta, m, v, grad, t, lr)
         hist.append(tot / max(cnt, 1))
-        its, rec, ok = solve_stats(theta, VALIDATION_IDS)
+        its, rec, ok = solve_stats(theta, val_ids)
         keep = ok and rec <= 1e-4 and its < best_its
         if keep:
             best, best_its = theta.clone(), its
@@ -208,15 +239,18 @@ if __name__ == "__main__":
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--lr", type=float, default=3e-4)
+    ap.add_argument("--test", type=int, default=64, help="held-out test instances 512, 513, ... after training")
+    ap.add_argument("--compare", default="", help="another parameter file to evaluate on the test instances")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
+    ap2_test = list(range(POOL, POOL + a.test))
     th, hist = train(a.instances, a.epochs, a.steps, lr=a.lr)
     save_theta(th, a.out)
-    test = list(range(512, 520))
-    print(f"held-out mean log loss: paper {evaluate(None, test, a.steps):.4f}  learned {evaluate(th, test, a.steps):.4f}",
-          flush=True)
-    # real (hard-threshold) solves on the held-out instances
-    for name, theta in (("paper", None), ("learned", th)):
-        its, rec, ok = solve_stats(theta, test)
-        print(f"held-out solves, {name}: {its:.2f} mean iterations, worst recovery {rec:.1e}, all converged {ok}",
-              flush=True)
+    print(f"held-out mean log loss (first 8): paper {evaluate(None, ap2_test[:8], a.steps):.4f}  "
+          f"learned {evaluate(th, ap2_test[:8], a.steps):.4f}", flush=True)
+    # real (hard-threshold) solves on the held-out test instances
+    others = [("compared", load_theta(a.compare))] if a.compare else []
+    for name, theta in [("paper", None), ("learned", th)] + others:
+        its, rec, ok = solve_stats(theta, ap2_test)
+        print(f"held-out solves ({len(ap2_test)} instances {ap2_test[0]}..{ap2_test[-1]}), {name}: {its:.3f} mean "
+              f"iterations, worst recovery {rec:.1e}, all converged {ok}", flush=True)

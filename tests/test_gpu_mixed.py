@@ -1,15 +1,15 @@
-"""Mixed-precision form (RPCA_FLAG_MIXED): of the row product
-Y1 = Z V_f = L V_f + E V_f (Z = D - S, E = D - L - S), the residual part E V_f
-runs on the matrix cores with BF16 operands and FP32 accumulation and the
-rank-r part L V_f is added exactly from the factors; the column product
-Y2 = Z^T U_f, the threshold and the residual in FP32, small algebra in FP64,
-as in the FP32 path.
+"""Mixed-precision form (RPCA_FLAG_MIXED): of the tangent products
+Y1 = Z V_f = L V_f + E V_f and Y2 = Z^T U_f = L^T U_f + E^T U_f (Z = D - S,
+E = D - L - S), the residual parts E V_f and E^T U_f run on the matrix cores
+with BF16 operands and FP32 accumulation and the rank-r parts are added
+exactly from the factors; the threshold and the residual in FP32, small
+algebra in FP64, as in the FP32 path.
 
 Parity unpinned by the paper (a precision choice of this implementation).
-Pins used instead: Y1 against an FP64 reference computed from the
+Pins used instead: Y1 and Y2 against FP64 references computed from the
 BF16-rounded operands (the kernel's own rounding, so agreement up to FP32
-accumulation is required); the error of Y1 against the exact product, which
-must scale with the size of E rather than with that of Z; Y2 and the
+accumulation is required); the errors of Y1 and Y2 against the exact
+products, which must scale with the size of E rather than with that of Z; the
 threshold residual against the FP64 oracle at the FP32 tolerance; and whole
 solves against the FP64 oracle and the ground truth at the 1e-4 level of the
 paper's success criterion (Section 4).
@@ -70,10 +70,11 @@ def test_mixed_tangent_products(m, n, r):
     Z = D - S
     E = np.where(np.abs(x) <= zeta, x, 0.0)
     res_o = float(np.sum(E * E))
-    # the operands of the matrix-core product: E and V_t rounded to BF16; the
-    # rank-r part L V_t = A (B^T V_t) is exact
-    Eb, Vb = bf16(E), bf16(Vt)
+    # the operands of the matrix-core products: E, V_t and U_t rounded to BF16;
+    # the rank-r parts L V_t = A (B^T V_t) and L^T U_t = B (A^T U_t) are exact
+    Eb, Vb, Ub = bf16(E), bf16(Vt), bf16(Ut)
     Y1b = Eb @ Vb + A @ (B.T @ Vt)
+    Y2b = Eb.T @ Ub + B @ (A.T @ Ut)
     Y1o, Y2o = Z @ Vt, Z.T @ Ut
     sv = R.Solver(dev(D, torch.float32), r, 0.01, 0.02, 0.5, 1.0, mixed=True)
     Y1, Y2, res = sv.tangent_products(dev(A), dev(B), zeta, dev(Ut), dev(Vt))
@@ -81,17 +82,18 @@ def test_mixed_tangent_products(m, n, r):
     # FP32 rebuild of L can move a value of E across a BF16 rounding boundary:
     # a few one-ulp differences of the operands, hence 1e-4 rather than FP32 eps
     assert rel(Y1, Y1b) < 1e-4, rel(Y1, Y1b)
-    # and the BF16 product is the exact product to BF16 accuracy
+    assert rel(Y2, Y2b) < 1e-4, rel(Y2, Y2b)
+    # and the BF16 products are the exact products to BF16 accuracy
     assert rel(Y1, Y1o) < 2e-2
-    # Y2 and the residual are the FP32 path's
-    assert rel(Y2, Y2o) < 2e-6, rel(Y2, Y2o)
+    assert rel(Y2, Y2o) < 2e-2
+    # the residual is the FP32 path's
     assert abs(res - res_o) / res_o < 2e-6
 
 
 @pytest.mark.parametrize("noise", [1e-2, 1e-4])
 def test_mixed_error_scales_with_residual(noise):
     """Near convergence D - L is small: the BF16 rounding then touches only
-    that small part, so Y1 keeps about the FP32 accuracy instead of the
+    that small part, so Y1 and Y2 keep about the FP32 accuracy instead of the
     2^-9 relative accuracy of a BF16 product of Z itself."""
     m, n, r = 777, 640, 5
     say(f"mixed tangent_products, D = L + noise {noise:g}")
@@ -103,11 +105,13 @@ def test_mixed_error_scales_with_residual(noise):
     Vt = f32(np.linalg.qr(rng.standard_normal((n, r)))[0])
     zeta = 1e6   # S = 0, Z = D, E = D - L
     sv = R.Solver(dev(D, torch.float32), r, 0.01, 0.02, 0.5, 1.0, mixed=True)
-    Y1, _, _ = sv.tangent_products(dev(A), dev(B), zeta, dev(Ut), dev(Vt))
+    Y1, Y2, _ = sv.tangent_products(dev(A), dev(B), zeta, dev(Ut), dev(Vt))
     err = rel(Y1.cpu().numpy(), D @ Vt)
-    say(f"relative error of Y1 {err:.2e}")
-    # BF16 rounding of E: ~2^-9 relative to |E| ~ noise, against |Y1| ~ 1
+    err2 = rel(Y2.cpu().numpy(), D.T @ Ut)
+    say(f"relative error of Y1 {err:.2e}, of Y2 {err2:.2e}")
+    # BF16 rounding of E: ~2^-9 relative to |E| ~ noise, against |Y| ~ 1
     assert err < 4e-3 * noise + 2e-6, err
+    assert err2 < 4e-3 * noise + 2e-6, err2
 
 
 def _plain_and_mixed(x, mixed_err, tol=None, max_iter=100):

@@ -13,6 +13,9 @@ the library uses for them:
   oracle run for the same K, within 1e-5 (FP32) and 1e-4 (mixed), and against
   the truth (Section 3's success bar 1e-4).
 
+* the largest instance of the runtime-against-n experiment (n = 15000, r = 5,
+  alpha = 0.1, tol 1e-4), FP32, against the oracle for the same K.
+
 Differences of rank-r matrices are formed from r x r products (no dense
 m x n difference). The oracle iterations print progress (about 12 s each at
 2 x 10^4 on the host).
@@ -182,3 +185,28 @@ def test_solves_2e4_r10_against_oracle_and_truth(c4):
     assert d_ref <= 1e-5
     assert d_mix <= 1e-4
     assert d_true <= 1e-4 and d_true_m <= 1e-4
+
+
+# ------------------------------------- Figure 2(a), the largest n -----
+
+def test_nsweep_largest_n_against_oracle():
+    """The largest instance of the runtime-against-n experiment of Section 3
+    (n = 15000, r = 5, alpha = 0.1, c = 1, stop at err_k < 1e-4; the seed of
+    the committed experiment results), FP32: the solve against the oracle run
+    for the same number of iterations, and against the truth."""
+    x = I.gaussian_instance(15000, 15000, 5, 0.1, 1.0, tol=1e-4, seed=I.seed_for(32, 15000), keep_L=False)
+    D = f32(x.D)
+    x.D = None
+    say(f"n = 15000 instance ready (r={x.r}, mu={x.mu:.2f})")
+    info, U, s, V = gpu_solve(dev(D, torch.float32), x)
+    K = info.iterations
+    say(f"GPU: {K} iterations, err {info.err:.2e}")
+    st, errs, zetas = oracle_fixed_k(D, x, K, "n=15000")
+    d_ref = rel_factored(U, s, V, st.U, st.sigma, st.V)
+    d_true = rel_factored(U, s, V, x.P, np.ones(x.r), x.Q)
+    say(f"rel L to oracle {d_ref:.2e}, recovery {d_true:.2e}")
+    assert info.status == R.RPCA_OK and info.err < x.tol
+    np.testing.assert_allclose(info.err_hist, errs, rtol=1e-3)
+    assert errs[-1] < x.tol and min(errs[:-1]) >= x.tol
+    assert d_ref <= 1e-5
+    assert d_true <= 1e-4
