@@ -254,6 +254,34 @@ int rpca_relaxed_step(const void *D, const rpca_params *p, rpca_state *st, doubl
                       const double *P_true, const double *Q_true, int32_t r_true,
                       rpca_relax_result *out, void *ws, size_t ws_bytes, void *stream);
 
+/* Reverse mode of K unrolled relaxed iterations (training through the
+ * iterations; not part of the paper). Body k (k = 0..K-1) is the iteration of
+ * rpca_relaxed_step from L_k = U_k diag(sigma_k) V_k^T with threshold zeta[k]
+ * and temperature tau[k] (Algorithm 1's body with s(x) in place of T_zeta:
+ * Trim of Algorithm 2, P_T and H_r of Section 2.1); the loss is
+ *   sum_{k=1..K} weight[k-1] ||L_k - P Q^T||_F^2 / ||P Q^T||_F^2.
+ * Checkpoints: U_ck[k], sigma_ck[k], V_ck[k] (k = 0..K; host arrays of K + 1
+ * device pointers, FP64, m x r / r / n x r, row stride r) are the factors of
+ * L_k as rpca_relaxed_step produced them (any factorisation for k = 0); only
+ * these are kept, and every body's intermediates are recomputed with one pass
+ * over D. zeta, tau, weight: host arrays of K. Outputs: zeta_bar (host, K):
+ * d loss / d zeta_k; U_bar, sigma_bar, V_bar (device, m x r, r, n x r): the
+ * gradient with respect to the factors of L_0 taken as free matrices. Between
+ * bodies the gradient is carried with respect to L_k and never formed as a
+ * dense matrix. The thresholds are inputs: a schedule that computes them from
+ * the iterates is differentiated with its features held fixed. Needs
+ * sigma_r > sigma_{r+1} of every P_T(Z) and full-rank complements; requires
+ * RPCA_FLAG_TRAINING (workspace), r <= 10, 1 <= K <= RPCA_MAX_UNROLL,
+ * 1 <= r_true <= 16, zeta[k] > 0, tau[k] > 0, finite weights, else
+ * RPCA_EINVAL. The call returns after the device work is done. */
+#define RPCA_MAX_UNROLL 64
+int rpca_unrolled_adjoint(const void *D, const rpca_params *p, int32_t K,
+                          const double *const *U_ck, const double *const *sigma_ck, const double *const *V_ck,
+                          const double *zeta, const double *tau, const double *weight,
+                          const double *P_true, const double *Q_true, int32_t r_true,
+                          double *zeta_bar, double *U_bar, double *sigma_bar, double *V_bar,
+                          void *ws, size_t ws_bytes, void *stream);
+
 /* Training kernels of the threshold network (device FP32 arrays, ordered
  * on stream; parameter layout W1 (32 x 4, row-major), b1 (32), W2 (32 x 32),
  * b2 (32), w3 (32), b3 (1), RPCA_MLP_PARAMS values):

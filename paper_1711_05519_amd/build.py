@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "librpca.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["stream.hip", "stream_mx.hip", "panel.hip", "relax.hip", "mlp.hip", "api.hip"]
+SOURCES = ["stream.hip", "stream_mx.hip", "panel.hip", "relax.hip", "adjoint.hip", "mlp.hip", "api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -297,6 +297,7 @@ struct Layout {
     // relaxed iteration (RPCA_FLAG_TRAINING)
     int rx_nct, rx_nrt, rx_TM;
     size_t off_R1, off_R2, off_Rres, off_RY1, off_RY2, off_gpR, off_gram, off_gram2, off_coef, off_rres;
+    size_t off_adj;   // reverse mode of unrolled relaxed iterations
     size_t total;
 };
 
@@ -347,7 +348,7 @@ Layout make_layout(const rpca_params* p) {
     L.off_AL = take(tm); L.off_BL = take(tn);
     L.rx_nct = L.rx_nrt = L.rx_TM = 0;
     L.off_R1 = L.off_R2 = L.off_Rres = L.off_RY1 = L.off_RY2 = L.off_gpR = L.off_gram = L.off_gram2 = 0;
-    L.off_coef = L.off_rres = 0;
+    L.off_coef = L.off_rres = L.off_adj = 0;
     if (p->flags & RPCA_FLAG_TRAINING) {
         const int K2 = 2 * p->r;
         L.rx_nct = (n + RX_THREADS - 1) / RX_THREADS;
@@ -366,6 +367,7 @@ Layout make_layout(const rpca_params* p) {
         L.off_gram2 = take(sizeof(double) * 2 * RX_WMAX * RX_WMAX);
         L.off_coef = take(sizeof(double) * 6 * KMAX * KMAX);
         L.off_rres = take(sizeof(RelaxResult));
+        L.off_adj = take(adjoint_ws_bytes(m, n, p->r, L.rx_nct, L.rx_nrt));
     }
     L.total = off;
     return L;
@@ -1196,6 +1198,62 @@ int rpca_relaxed_step(const void* D, const rpca_params* p, rpca_state* st, doubl
     st->sigma1_pt = r.sigma1;
     st->sigma_r1_pt = r.sigma_r1;
     st->normD = sqrt(nd2);
+    return RPCA_OK;
+}
+
+int rpca_unrolled_adjoint(const void* D, const rpca_params* p, int32_t K, const double* const* U_ck,
+                          const double* const* sigma_ck, const double* const* V_ck, const double* zeta,
+                          const double* tau, const double* weight, const double* P_true, const double* Q_true,
+                          int32_t r_true, double* zeta_bar, double* U_bar, double* sigma_bar, double* V_bar, void* ws,
+                          size_t ws_bytes, void* stream) {
+    if (!D || !U_ck || !sigma_ck || !V_ck || !zeta || !tau || !weight || !P_true || !Q_true || !zeta_bar || !U_bar ||
+        !sigma_bar || !V_bar)
+        return RPCA_EINVAL;
+    if (!p || !(p->flags & RPCA_FLAG_TRAINING)) return RPCA_EINVAL;
+    if (K < 1 || K > RPCA_MAX_UNROLL || r_true < 1 || r_true > RX_TRUE_MAX) return RPCA_EINVAL;
+    for (int k = 0; k <= K; ++k)
+        if (!U_ck[k] || !sigma_ck[k] || !V_ck[k]) return RPCA_EINVAL;
+    for (int k = 0; k < K; ++k)
+        if (!is_fin(zeta[k]) || !(zeta[k] > 0) || !is_fin(tau[k]) || !(tau[k] > 0) || !is_fin(weight[k]))
+            return RPCA_EINVAL;
+    Ctx c;
+    RPCA_TRY(make_ctx(p, ws, ws_bytes, stream, &c));
+    const Layout& L = c.L;
+    AdjointBufs B;
+    HIP_TRY(adjoint_carve(c.ws + L.off_adj, p->m, p->n, p->r, L.rx_nct, L.rx_nrt, &B));
+    AdjointProblem P;
+    memset(&P, 0, sizeof(P));
+    P.D = D;
+    P.ldd = p->ldd;
+    P.m = p->m;
+    P.n = p->n;
+    P.dtype = c.dtype;
+    P.K = p->r;
+    P.Kt = K;
+    P.rt = r_true;
+    P.P = P_true;
+    P.Q = Q_true;
+    P.U = U_ck;
+    P.sigma = sigma_ck;
+    P.V = V_ck;
+    P.zeta = zeta;
+    P.tau = tau;
+    P.weight = weight;
+    const bool trim = !(p->flags & RPCA_FLAG_NO_TRIM);
+    P.cU = trim ? sqrt(p->mu * (double)p->r / (double)p->m) : 0.0;
+    P.cV = trim ? sqrt(p->mu * (double)p->r / (double)p->n) : 0.0;
+    P.TM = L.rx_TM;
+    P.n_ct = L.rx_nct;
+    P.n_rt = L.rx_nrt;
+    P.zeta_bar_dev = B.zbar;
+    P.U_bar = U_bar;
+    P.sigma_bar = sigma_bar;
+    P.V_bar = V_bar;
+    HIP_TRY(adjoint_run(P, B, c.s));
+    std::vector<double> zb((size_t)K);
+    HIP_TRY(hipMemcpyAsync(zb.data(), B.zbar, sizeof(double) * (size_t)K, hipMemcpyDeviceToHost, c.s));
+    HIP_TRY(hipStreamSynchronize(c.s));
+    for (int k = 0; k < K; ++k) zeta_bar[k] = zb[(size_t)k];
     return RPCA_OK;
 }
 

@@ -128,6 +128,42 @@ hipError_t launch_start(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, hipStream_t s);
 hipError_t launch_enter_loop(Ctrl* ctrl, hipStream_t s);
 hipError_t launch_relax(const RelaxArgs& a, int dtype, hipStream_t s);
+
+// Reverse mode of unrolled relaxed iterations (adjoint.hip).
+struct AdjointProblem {
+    const void* D;
+    int64_t ldd, m, n;
+    int32_t dtype, K, Kt, rt;                 // rank, bodies, rank of the target factors
+    const double* P;                          // target factors, m x rt and n x rt
+    const double* Q;
+    const double* const* U;                   // host arrays of Kt + 1 device checkpoints
+    const double* const* sigma;
+    const double* const* V;
+    const double* zeta;                       // host arrays of Kt
+    const double* tau;
+    const double* weight;
+    double cU, cV;                            // trim levels (0: no trim)
+    int32_t TM, n_ct, n_rt;                   // tiling of the passes over D
+    double* zeta_bar_dev;                     // device outputs
+    double* U_bar;
+    double* sigma_bar;
+    double* V_bar;
+};
+struct AdjointBufs {
+    struct Slot {
+        double *Am, *wU, *rhoU, *BU, *Bm, *wV, *rhoV, *BV;
+        double *RAinv, *RBinv, *C, *R1, *R2, *R1inv, *R2inv, *UM, *SM, *VM;
+    } slot[2];
+    double *Y1, *W1, *GammaV, *YG, *SR, *GU, *Abar, *Utrim, *F1;
+    double *Y2, *W2, *GammaU, *XG, *SC, *GV, *Bbar, *Vtrim, *F2;
+    double *Rp, *Cp, *scal, *scal_out, *gpart, *small;
+    double* zbar;                             // dloss/dzeta_k, RPCA_MAX_UNROLL values
+    uint32_t* cnt;
+    char* end;
+};
+size_t adjoint_ws_bytes(int64_t m, int64_t n, int K, int n_ct, int n_rt);
+hipError_t adjoint_carve(void* base, int64_t m, int64_t n, int K, int n_ct, int n_rt, AdjointBufs* b);
+hipError_t adjoint_run(const AdjointProblem& P, const AdjointBufs& B, hipStream_t s);
 hipError_t launch_mlp_forward(const float* th, const float* phi, float* o, int B, hipStream_t s);
 hipError_t launch_mlp_backward(const float* th, const float* phi, const float* g, int B, float* grad, hipStream_t s);
 hipError_t launch_mlp_adam(float* th, float* m, float* v, const float* g, int t, float lr, float b1, float b2,

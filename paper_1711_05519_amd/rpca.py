@@ -38,7 +38,7 @@ EXPORTED = ("rpca_workspace_size", "rpca_init", "rpca_trim", "rpca_step", "rpca_
             "rpca_solve_many",
             "rpca_materialize", "rpca_tangent_products", "rpca_strerror",
             "rpca_last_hip_error", "rpca_version", "rpca_profile_enable", "rpca_profile_read",
-            "rpca_relaxed_step", "rpca_mlp_forward", "rpca_mlp_backward", "rpca_mlp_adam", "rpca_read_probe")
+            "rpca_relaxed_step", "rpca_unrolled_adjoint", "rpca_mlp_forward", "rpca_mlp_backward", "rpca_mlp_adam", "rpca_read_probe")
 
 
 class RpcaError(RuntimeError):
@@ -99,6 +99,8 @@ def _lib():
             "rpca_materialize": [vp, P, S, vp, ctypes.c_int64, vp, ctypes.c_int64, vp, sz, vp],
             "rpca_tangent_products": [vp, P, vp, vp, d, vp, vp, vp, vp, pd, vp, sz, vp],
             "rpca_relaxed_step": [vp, P, S, d, d, vp, vp, ctypes.c_int32, ctypes.POINTER(RelaxResult), vp, sz, vp],
+            "rpca_unrolled_adjoint": [vp, P, ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      pd, pd, pd, vp, vp, ctypes.c_int32, pd, vp, vp, vp, vp, sz, vp],
             "rpca_mlp_forward": [vp, vp, ctypes.c_int32, vp, vp],
             "rpca_read_probe": [vp, ctypes.c_int64, vp, vp],
             "rpca_mlp_backward": [vp, vp, vp, ctypes.c_int32, vp, vp],
@@ -191,6 +193,35 @@ def rpca_relaxed_step(D, params, state, zeta, tau, P, Q, ws, stream=None) -> Rel
                                     _ptr(P), _ptr(Q), int(P.shape[1]), ctypes.byref(out), w, nb, _stream(stream)),
            "rpca_relaxed_step")
     return out
+
+
+RPCA_MAX_UNROLL = 64
+
+
+def rpca_unrolled_adjoint(D, params, Us, ss, Vs, zetas, taus, weights, P, Q, U_bar, s_bar, V_bar, ws,
+                          stream=None) -> np.ndarray:
+    """Reverse mode of K unrolled relaxed iterations (see include/rpca.h).
+    Us, ss, Vs: the K + 1 checkpoints (FP64 device tensors); zetas, taus,
+    weights: K values; P, Q: FP64 device target factors; U_bar, s_bar, V_bar:
+    FP64 device outputs. Returns d loss / d zeta_k (K values)."""
+    K = len(zetas)
+    if not (len(Us) == len(ss) == len(Vs) == K + 1 and len(taus) == K and len(weights) == K):
+        raise ValueError("K + 1 checkpoints and K thresholds, temperatures and weights are required")
+    if P.dtype != torch.float64 or Q.dtype != torch.float64 or P.shape[1] != Q.shape[1]:
+        raise ValueError("P and Q must be FP64 with the same number of columns")
+    for t in list(Us) + list(ss) + list(Vs) + [U_bar, s_bar, V_bar]:
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("checkpoints and outputs must be contiguous FP64 device tensors")
+    P, Q = P.contiguous(), Q.contiguous()
+    arr = lambda ts: (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+    dbl = lambda xs: (ctypes.c_double * len(xs))(*[float(x) for x in xs])
+    zb = (ctypes.c_double * K)()
+    w, nb = _ws(ws)
+    _check(_lib().rpca_unrolled_adjoint(_ptr(D), ctypes.byref(params), K, arr(Us), arr(ss), arr(Vs), dbl(zetas),
+                                        dbl(taus), dbl(weights), _ptr(P), _ptr(Q), int(P.shape[1]), zb,
+                                        _ptr(U_bar), _ptr(s_bar), _ptr(V_bar), w, nb, _stream(stream)),
+           "rpca_unrolled_adjoint")
+    return np.array(zb[:], dtype=np.float64)
 
 
 def _f32(t, n=None):
@@ -439,6 +470,26 @@ class Solver:
         """One relaxed iteration from the current state (needs training=True)."""
         return rpca_relaxed_step(self.D, self.params, self.state, zeta, tau, P, Q, self.ws)
 
+    def unrolled(self, zetas, taus, weights, P: torch.Tensor, Q: torch.Tensor):
+        """K relaxed iterations from the current state (which advances to L_K),
+        keeping the factor checkpoints. Returns (losses, checkpoints)."""
+        ck = [(self.U.clone(), self.sigma.clone(), self.V.clone())]
+        losses = []
+        for z, t in zip(zetas, taus):
+            res = self.relaxed_step(float(z), float(t), P, Q)
+            losses.append(res.loss)
+            ck.append((self.U.clone(), self.sigma.clone(), self.V.clone()))
+        return losses, ck
+
+    def unrolled_adjoint(self, checkpoints, zetas, taus, weights, P: torch.Tensor, Q: torch.Tensor):
+        """Gradients of sum_k weights[k-1] loss_k over the iterations that
+        produced `checkpoints`: (d/dzeta (K values), dU_0, dsigma_0, dV_0)."""
+        U0, s0, V0 = checkpoints[0]
+        Ub, sb, Vb = torch.empty_like(U0), torch.empty_like(s0), torch.empty_like(V0)
+        zb = rpca_unrolled_adjoint(self.D, self.params, [c[0] for c in checkpoints], [c[1] for c in checkpoints],
+                                   [c[2] for c in checkpoints], zetas, taus, weights, P, Q, Ub, sb, Vb, self.ws)
+        return zb, Ub, sb, Vb
+
     def get_state(self):
         """(U, sigma, V, zeta, k, normD) copies of the current state."""
         return (self.U.clone(), self.sigma.clone(), self.V.clone(), self.state.zeta, self.state.k,
@@ -471,6 +522,34 @@ def solve_many(solvers, n_streams: int = 8) -> list:
                              zeta_hist=list(z[:k + 1]), init_passes=sv.state.init_passes,
                              svd_sweeps=sv.state.svd_sweeps))
     return out
+
+
+class UnrolledRelaxed(torch.autograd.Function):
+    """loss = UnrolledRelaxed.apply(zetas, U0, sigma0, V0, solver, P, Q, taus, weights):
+    K = len(zetas) relaxed iterations of `solver` from L_0 = U0 diag(sigma0) V0^T
+    (the solver's state ends at L_K) and the weighted loss
+    sum_k weights[k-1] ||L_k - P Q^T||^2 / ||P Q^T||^2. Backward runs the
+    library's reverse sweep over the iterations from the factor checkpoints:
+    gradients for the thresholds and for the initial factors."""
+
+    @staticmethod
+    def forward(ctx, zetas, U0, sigma0, V0, solver, P, Q, taus, weights):
+        z = [float(v) for v in zetas.detach().cpu()]
+        solver.U.copy_(U0.detach())
+        solver.sigma.copy_(sigma0.detach())
+        solver.V.copy_(V0.detach())
+        losses, ck = solver.unrolled(z, taus, weights, P, Q)
+        ctx.solver, ctx.ck, ctx.z = solver, ck, z
+        ctx.taus, ctx.weights, ctx.P, ctx.Q = list(taus), list(weights), P, Q
+        ctx.losses = losses
+        return torch.tensor(sum(w * l for w, l in zip(weights, losses)), dtype=torch.float64, device=zetas.device)
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        zb, Ub, sb, Vb = ctx.solver.unrolled_adjoint(ctx.ck, ctx.z, ctx.taus, ctx.weights, ctx.P, ctx.Q)
+        g = grad_loss.to(torch.float64)
+        gz = torch.as_tensor(zb, dtype=torch.float64, device=grad_loss.device) * g
+        return gz, Ub * g, sb * g, Vb * g, None, None, None, None, None
 
 
 class RelaxedStep(torch.autograd.Function):
