@@ -87,8 +87,9 @@ extern "C" {
  * = beta (sigma_{r+1} + gamma^{k+1} sigma_1) * exp(clip(o, -5, 5)), a learned
  * correction of Algorithm 1's threshold, with o the output of the threshold
  * network (params->zeta_mlp, RPCA_MLP_PARAMS device floats) at the features
- *   phi = ((k + 1) / 15, log(sigma_{r+1} / sigma_1), log err_k, log(sigma_1 / ||D||_F)),
- * sigma_1, sigma_{r+1} those of P_T(D - S_k). Fallback to the paper's
+ *   phi = ((k + 1) / 15, log max(sigma_{r+1} / sigma_1, 1e-4), log err_k, log(sigma_1 / ||D||_F)),
+ * sigma_1, sigma_{r+1} those of P_T(D - S_k) (the ratio is clamped where the
+ * FP32 path no longer resolves sigma_{r+1}). Fallback to the paper's
  * schedule of Algorithm 1 for the rest of the solve as soon as err_k >= err_{k-1}
  * or the network's threshold is not a positive finite number. */
 #define RPCA_FLAG_LEARNED 8u

@@ -37,6 +37,10 @@ N_IN, N_H = 4, 32
 SIZES = (N_H * N_IN, N_H, N_H * N_H, N_H, N_H, 1)
 N_PARAMS = sum(SIZES)          # 1249
 FEATURE_FLOOR = 1e-30          # floor inside the logarithms of the features
+# sigma_{r+1} / sigma_1 is clamped from below: a library that computes the
+# singular values of M in FP32 products resolves sigma_{r+1} only to about
+# 1e-5 sigma_1, so smaller ratios would feed rounding noise to the network
+SIGMA_RATIO_FLOOR = 1e-4
 
 
 def unpack(theta: np.ndarray):
@@ -51,10 +55,10 @@ def unpack(theta: np.ndarray):
 
 
 def features(k: int, K: int, sigma1: float, sigma_r1: float, err: float, normD: float) -> np.ndarray:
-    """phi_k = (k / K, log(sigma_{r+1} / sigma_1), log err_k, log(sigma_1 / ||D||_F))."""
+    """phi_k = (k / K, log max(sigma_{r+1} / sigma_1, 1e-4), log err_k, log(sigma_1 / ||D||_F))."""
     f = FEATURE_FLOOR
     return np.array([k / K,
-                     np.log(max(sigma_r1, f) / max(sigma1, f)),
+                     np.log(max(sigma_r1 / max(sigma1, f), SIGMA_RATIO_FLOOR)),
                      np.log(max(err, f)),
                      np.log(max(sigma1, f) / max(normD, f))], dtype=np.float64)
 
@@ -205,7 +209,7 @@ def learned_solve(D: np.ndarray, p: A.Params, theta: np.ndarray | None, max_iter
 
       zeta_{k+1} = zeta_paper * exp(clip(o_k, -5, 5)),
       zeta_paper = beta (sigma_{r+1} + gamma^{k+1} sigma_1)   (Algorithm 1),
-      o_k = network(phi_k),  phi_k = ((k + 1) / 15, log(sigma_{r+1} / sigma_1),
+      o_k = network(phi_k),  phi_k = ((k + 1) / 15, log max(sigma_{r+1} / sigma_1, 1e-4),
                                       log err_k, log(sigma_1 / ||D||_F)),
 
     with sigma_1, sigma_{r+1} those of P_T(D - S_k) (the 2r x 2r matrix of

@@ -27,6 +27,9 @@ constexpr int RX_WMAX = 3 * RX_KMAX + RX_TRUE_MAX;   // widest Gram, [F Y dY P]
 constexpr int MLP_IN = 4, MLP_H = 32;
 constexpr int MLP_PARAMS = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;   // 1249
 constexpr double MLP_K_FEAT = 15.0;   // iteration count that normalises the first feature
+// sigma_{r+1} / sigma_1 enters the features clamped from below: the FP32 path
+// resolves sigma_{r+1} only to about 1e-5 sigma_1, so smaller ratios are noise
+constexpr double MLP_SIGMA_RATIO_FLOOR = 1e-4;
 
 // Stages of the device-side state machine (Ctrl::stage).
 enum Stage : int {

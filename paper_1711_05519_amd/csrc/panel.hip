@@ -253,7 +253,7 @@ __device__ __forceinline__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const
         const double f = 1e-30;
         double phi[MLP_IN];
         phi[0] = (ctrl->k + 1) / MLP_K_FEAT;
-        phi[1] = log(fmax(sg[r], f) / fmax(sg[0], f));
+        phi[1] = log(fmax(sg[r] / fmax(sg[0], f), MLP_SIGMA_RATIO_FLOOR));
         phi[2] = log(fmax(ctrl->err, f));
         phi[3] = log(fmax(sg[0], f) / fmax(sqrt(ctrl->normD2), f));
         mlp_o = w_mlp(a.mlp, phi);

@@ -55,6 +55,10 @@ def test_features():
     f = Lr.features(3, 15, sigma1=100.0, sigma_r1=1.0, err=1e-2, normD=1e4)
     assert np.allclose(f, [0.2, np.log(0.01), np.log(1e-2), np.log(0.01)])
     assert np.isfinite(Lr.features(0, 15, 1.0, 0.0, 0.0, 1.0)).all()
+    # sigma_{r+1} / sigma_1 is clamped at 1e-4 (unresolved below in FP32)
+    assert Lr.features(1, 15, 1.0, 1e-9, 1e-3, 1.0)[1] == pytest.approx(np.log(1e-4))
+    assert Lr.features(1, 15, 2.0, 0.0, 1e-3, 1.0)[1] == pytest.approx(np.log(1e-4))
+    assert Lr.features(1, 15, 2.0, 4e-4, 1e-3, 1.0)[1] == pytest.approx(np.log(2e-4))
 
 
 def test_soft_threshold_limit_and_derivative():
