@@ -208,6 +208,35 @@ int rpca_solve_many(int32_t count, const void *const *D, const rpca_params *cons
                     void *const *ws, const size_t *ws_bytes, void *const *streams, int32_t n_streams,
                     int32_t *status);
 
+/* Batched solve: count instances of one shape in every kernel launch
+ * (Algorithm 3, then Algorithm 1, for each instance; not part of the paper: a
+ * throughput form for many small problems). p[count]: the instances'
+ * parameters; they may differ in beta, beta_init, gamma, mu and tol and must
+ * agree in everything else (shape, r, dtype, flags, caps, seed). Instance i
+ * owns the slab that starts i * slab_bytes after `slabs` (device, 256-byte
+ * aligned), laid out as rpca_batch_layout_of reports: its D (m x n, row stride
+ * p->ldd, p->dtype) at off_D, filled by the caller; its iterate U (m x r), V
+ * (n x r), sigma (r), FP64, at off_U, off_V, off_sigma, written by the call;
+ * its workspace at off_ws. Each kernel launch covers all instances (grid y)
+ * and each instance's control block gates its own work, so every instance
+ * follows exactly the steps of rpca_solve (same stopping rule; with
+ * RPCA_FLAG_MIXED every loop body takes BF16 products, so mixed_err must be
+ * <= 0; with RPCA_FLAG_LEARNED the network p->zeta_mlp is shared).
+ * st[count] (host) receives each instance's scalars and pointers to its
+ * factors in its slab; err_hist / zeta_hist (host, count x hist_cap, row i for
+ * instance i, may be NULL) entries 0..st[i].k; status[i] the status
+ * rpca_solve would return. Returns RPCA_OK or the first negative instance
+ * status; RPCA_EINVAL for bad arguments (1 <= count <= RPCA_BATCH_MAX). Returns
+ * after the device work is done. */
+typedef struct rpca_batch_layout {
+    size_t slab_bytes;               /* bytes per instance (a multiple of 256)         */
+    size_t off_D, off_U, off_V, off_sigma, off_ws;   /* offsets inside a slab          */
+} rpca_batch_layout;
+#define RPCA_BATCH_MAX 65535
+int rpca_batch_layout_of(const rpca_params *p, rpca_batch_layout *out);   /* the same for every instance */
+int rpca_solve_batch(int32_t count, void *slabs, const rpca_params *p, rpca_state *st,
+                     double *err_hist, double *zeta_hist, int32_t hist_cap, int32_t *status, void *stream);
+
 /* Dense outputs of Algorithm 1: L_out = U diag(sigma) V^T (row stride ldl) and
  * S_out = T_zeta(D - L) (row stride lds), dtype elements, device. Either
  * pointer may be NULL. st is read only. */

@@ -386,6 +386,8 @@ struct Ctx {
     HostStatus* st_host = nullptr;   // the call's status slot (queues of bodies only)
     HostStatus* st_dev = nullptr;
     bool events = true;              // false: no profiler events (rpca_step_noalloc)
+    int32_t batch = 1;               // instances per launch (rpca_solve_batch); all pointers are instance 0's
+    int64_t slab = 0;                // bytes between the instances
     Ctrl* ctrl() const { return reinterpret_cast<Ctrl*>(ws + L.off_ctrl); }
     Small* small() const { return reinterpret_cast<Small*>(ws + L.off_small); }
     double* err_hist() const { return reinterpret_cast<double*>(ws + L.off_hist); }
@@ -409,8 +411,9 @@ int make_ctx(const rpca_params* p, void* ws, size_t ws_bytes, void* stream, Ctx*
     return RPCA_OK;
 }
 
-Ctrl base_ctrl(const Ctx& c, int stage, double zeta, int k, double normD2, int want_stop) {
-    const rpca_params* p = c.p;
+Ctrl base_ctrl(const Ctx& c, int stage, double zeta, int k, double normD2, int want_stop,
+               const rpca_params* own = nullptr) {
+    const rpca_params* p = own ? own : c.p;
     Ctrl t;
     memset(&t, 0, sizeof(t));
     t.stage = stage;
@@ -449,7 +452,17 @@ Geo geo_for(const Ctx& c, int K, bool rebuild, bool mx = false) {
     const int m = (int)c.p->m;
     const int occ = mx ? stream_mx_occupancy(K, rebuild) : stream_occupancy(K, c.dtype, rebuild);
     const int slots = occ * c.dev->cus;
-    int n_rt = n_rt_for(m, c.L.n_ct, slots < STREAM_MAX_SLOTS ? slots : STREAM_MAX_SLOTS);
+    int n_rt;
+    if (c.batch > 1) {
+        // a batch: at least two rounds of workgroups over all its instances, so
+        // that the last, partly filled round is a small part of the pass
+        const int64_t per = (int64_t)c.L.n_ct * c.batch;
+        const int want = (int)((2 * (int64_t)slots + per - 1) / per);
+        n_rt = n_rt_for(m, c.L.n_ct, want * c.L.n_ct);
+        if (n_rt > c.L.n_rt_max) n_rt = c.L.n_rt_max;
+    } else {
+        n_rt = n_rt_for(m, c.L.n_ct, slots < STREAM_MAX_SLOTS ? slots : STREAM_MAX_SLOTS);
+    }
     int TM = (m + n_rt - 1) / n_rt;
     TM = (TM + STREAM_WAVES - 1) / STREAM_WAVES * STREAM_WAVES;
     Geo g;
@@ -477,8 +490,10 @@ StreamArgs stream_args(const Ctx& c, const void* D, int body, const Geo& g) {
     a.n_ct = c.L.n_ct;
     a.n_rt = g.n_rt;
     const size_t row_bytes = (size_t)c.p->ldd * c.L.elt;
-    a.vec_ok = (((uintptr_t)D & 15u) == 0 && (row_bytes & 15u) == 0) ? 1 : 0;
+    a.vec_ok = (((uintptr_t)D & 15u) == 0 && (row_bytes & 15u) == 0 && (c.slab & 15) == 0) ? 1 : 0;
     a.body = body;
+    a.batch = c.batch;
+    a.slab = c.slab;
     return a;
 }
 
@@ -512,11 +527,13 @@ PanelArgs panel_args(const Ctx& c, const Geo& g = Geo{0, 1}) {
     a.body_id = 0;
     a.body = BODY_ANY;
     a.mlp = (c.p->flags & RPCA_FLAG_LEARNED) ? c.p->zeta_mlp : nullptr;
+    a.batch = c.batch;
+    a.slab = c.slab;
     return a;
 }
 
 int setup(const Ctx& c, const Ctrl& t) {
-    HIP_TRY(launch_setup(c.ctrl(), t, c.s));
+    HIP_TRY(launch_setup(c.ctrl(), t, c.batch, c.slab, c.s));
     return RPCA_OK;
 }
 
@@ -933,7 +950,7 @@ private:
                 // L_0: the leading r columns of the converged block; Trim and bases
                 RPCA_TRY(enqueue_enter(c_, c_.at<double>(c_.L.off_Unew), c_.at<double>(c_.L.off_Vnew), P_,
                                        c_.small()->sigma_new, st_->U, st_->V, st_->sigma));
-                HIP_TRY(launch_enter_loop(c_.ctrl(), c_.s));
+                HIP_TRY(launch_enter_loop(c_.ctrl(), 1, 0, c_.s));
                 in_loop_ = true;
                 loop_first_ = b_ + 1;
             }
@@ -1041,6 +1058,172 @@ int rpca_solve_many(int32_t count, const void* const* D, const rpca_params* cons
                 }
             }
             t_idle = std::chrono::steady_clock::now();
+        }
+    }
+    return first_err;
+}
+
+int rpca_batch_layout_of(const rpca_params* p, rpca_batch_layout* out) {
+    if (!out) return RPCA_EINVAL;
+    RPCA_TRY(validate(p));
+    const Layout L = make_layout(p);
+    const size_t elt = p->dtype == RPCA_F32 ? 4 : 8;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+    out->off_D = take(elt * (size_t)p->m * (size_t)p->ldd);
+    out->off_U = take(sizeof(double) * (size_t)p->m * p->r);
+    out->off_V = take(sizeof(double) * (size_t)p->n * p->r);
+    out->off_sigma = take(sizeof(double) * p->r);
+    out->off_ws = take(L.total);
+    out->slab_bytes = off;
+    return RPCA_OK;
+}
+
+// Every launch of the solve covers all instances (grid y); each instance's
+// control block gates its own work, so instances that have finished a stage
+// turn the later launches into no-ops. The host queues bodies a few at a time
+// and reads all control blocks in between (one strided copy).
+static_assert(sizeof(Ctrl) % 8 == 0, "control blocks are copied in 4-byte words, rows stay 8-byte aligned");
+
+// Mapped, coherent host memory for one call (device view through dev()).
+class MappedBuffer {
+public:
+    explicit MappedBuffer(size_t bytes) {
+        if (hipHostMalloc(&h_, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+            h_ = nullptr;
+            return;
+        }
+        if (hipHostGetDevicePointer(&d_, h_, 0) != hipSuccess) d_ = nullptr;
+    }
+    ~MappedBuffer() {
+        if (h_) (void)hipHostFree(h_);
+    }
+    MappedBuffer(const MappedBuffer&) = delete;
+    MappedBuffer& operator=(const MappedBuffer&) = delete;
+    bool ok() const { return h_ && d_; }
+    void* host() const { return h_; }
+    void* dev() const { return d_; }
+
+private:
+    void* h_ = nullptr;
+    void* d_ = nullptr;
+};
+
+// Fields that every instance of a batch must share (one launch shape).
+bool same_shape(const rpca_params* a, const rpca_params* b) {
+    return a->m == b->m && a->n == b->n && a->ldd == b->ldd && a->r == b->r && a->dtype == b->dtype &&
+           a->max_iter == b->max_iter && a->init_block == b->init_block &&
+           a->init_max_passes == b->init_max_passes && a->flags == b->flags && a->seed == b->seed &&
+           a->mixed_err == b->mixed_err && a->zeta_mlp == b->zeta_mlp;
+}
+
+int rpca_solve_batch(int32_t count, void* slabs, const rpca_params* params, rpca_state* st, double* err_hist,
+                     double* zeta_hist, int32_t hist_cap, int32_t* status, void* stream) {
+    if (count < 1 || !slabs || !params || !st || !status || hist_cap < 0 || ((uintptr_t)slabs & 255u) != 0)
+        return RPCA_EINVAL;
+    if (count > RPCA_BATCH_MAX) return RPCA_EINVAL;
+    for (int32_t i = 0; i < count; ++i) status[i] = RPCA_EINVAL;
+    const rpca_params* p = &params[0];
+    for (int32_t i = 0; i < count; ++i) {
+        RPCA_TRY(validate(&params[i]));
+        if (!same_shape(p, &params[i])) return RPCA_EINVAL;
+    }
+    if ((p->flags & RPCA_FLAG_MIXED) && p->mixed_err > 0) return RPCA_EINVAL;
+    rpca_batch_layout bl;
+    RPCA_TRY(rpca_batch_layout_of(p, &bl));
+    char* base = static_cast<char*>(slabs);
+    Ctx c;
+    RPCA_TRY(make_ctx(p, base + bl.off_ws, make_layout(p).total, stream, &c));
+    c.batch = count;
+    c.slab = (int64_t)bl.slab_bytes;
+    c.events = false;
+    const void* D0 = base + bl.off_D;
+    double* U0 = reinterpret_cast<double*>(base + bl.off_U);
+    double* V0 = reinterpret_cast<double*>(base + bl.off_V);
+    double* s0 = reinterpret_cast<double*>(base + bl.off_sigma);
+    // Control blocks and histories pass through mapped host memory, moved by a
+    // kernel (one row per instance)
+    const int cnt_h = hist_cap < p->max_iter + 1 ? hist_cap : p->max_iter + 1;
+    const size_t row = sizeof(Ctrl) + 2 * sizeof(double) * (size_t)(cnt_h > 0 ? cnt_h : 0);
+    MappedBuffer hb(row * (size_t)count);
+    if (!hb.ok()) {
+        g_last_hip_error = (int)hipErrorOutOfMemory;
+        return RPCA_EHIP;
+    }
+    Ctrl* ctl = reinterpret_cast<Ctrl*>(hb.host());
+    auto read_all = [&]() -> int {
+        HIP_TRY(launch_slab_copy(c.ctrl(), c.slab, hb.dev(), (int64_t)row, sizeof(Ctrl), count, 0, c.s));
+        HIP_TRY(hipStreamSynchronize(c.s));
+        std::atomic_thread_fence(std::memory_order_acquire);
+        return RPCA_OK;
+    };
+    auto at = [&](int32_t i) -> Ctrl& { return *reinterpret_cast<Ctrl*>(reinterpret_cast<char*>(ctl) + row * i); };
+    // Algorithm 3. Each instance's control block carries its own beta,
+    // beta_init, gamma, mu and tol.
+    const int P = c.L.K_init;
+    const Ctrl t = base_ctrl(c, STAGE_SIGMA_D, INFINITY, 0, 1.0, 0);
+    for (int32_t i = 0; i < count; ++i) at(i) = base_ctrl(c, STAGE_SIGMA_D, INFINITY, 0, 1.0, 0, &params[i]);
+    std::atomic_thread_fence(std::memory_order_release);
+    HIP_TRY(launch_slab_copy(c.ctrl(), c.slab, hb.dev(), (int64_t)row, sizeof(Ctrl), count, 1, c.s));
+    HIP_TRY(hipStreamSynchronize(c.s));
+    PanelArgs sa = panel_args(c);
+    sa.seed = p->seed;
+    HIP_TRY(launch_start(sa, P, c.dtype, c.s));
+    const int max_init = 2 * t.init_max_passes + 4;
+    for (int b = 0; b < max_init;) {
+        const int chunk = b == 0 ? 4 : 2;
+        for (int j = 0; j < chunk && b < max_init; ++j, ++b)
+            RPCA_TRY(enqueue_body(c, D0, P, BODY_INIT, nullptr, nullptr, nullptr, false, false, 0));
+        RPCA_TRY(read_all());
+        bool all = true;
+        for (int32_t i = 0; i < count; ++i) all = all && at(i).stage >= STAGE_INIT_DONE;
+        if (all) break;
+    }
+    RPCA_TRY(enqueue_enter(c, c.at<double>(c.L.off_Unew), c.at<double>(c.L.off_Vnew), P, c.small()->sigma_new, U0,
+                           V0, s0));
+    HIP_TRY(launch_enter_loop(c.ctrl(), c.batch, c.slab, c.s));
+    // Algorithm 1 (the device's stopping rule ends each instance)
+    const int max_main = p->max_iter + 3;
+    for (int b = 0; b < max_main;) {
+        const int chunk = b < 4 ? 4 : 2;
+        for (int j = 0; j < chunk && b < max_main; ++j, ++b)
+            RPCA_TRY(enqueue_body(c, D0, p->r, BODY_MAIN, U0, V0, s0, true, c.mixed, 0));
+        RPCA_TRY(read_all());
+        bool all = true;
+        for (int32_t i = 0; i < count; ++i) all = all && at(i).done != 0;
+        if (all) break;
+    }
+    RPCA_TRY(read_all());
+    int first_err = RPCA_OK;
+    for (int32_t i = 0; i < count; ++i) {
+        const Ctrl f = at(i);
+        char* bi = base + (size_t)i * bl.slab_bytes;
+        int si;
+        if (f.nonfinite == 1) si = RPCA_EINVAL;
+        else if (f.nonfinite) si = RPCA_EBREAKDOWN;
+        else if (f.stage != STAGE_MAIN || !f.done) si = RPCA_EHIP;
+        else si = f.stopped_by_tol ? RPCA_OK : RPCA_MAXITER;
+        status[i] = si;
+        if (si < 0 && first_err == RPCA_OK) first_err = si;
+        st[i].U = reinterpret_cast<double*>(bi + bl.off_U);
+        st[i].V = reinterpret_cast<double*>(bi + bl.off_V);
+        st[i].sigma = reinterpret_cast<double*>(bi + bl.off_sigma);
+        fill_state(&st[i], f);
+        st[i].init_passes = f.total_passes;
+        st[i].reserved = 0;
+    }
+    if (cnt_h > 0 && (err_hist || zeta_hist)) {
+        // err and zeta histories are adjacent in the workspace: one row each
+        char* h0 = static_cast<char*>(hb.dev()) + sizeof(Ctrl);
+        HIP_TRY(launch_slab_copy(c.err_hist(), c.slab, h0, (int64_t)row, sizeof(double) * cnt_h, count, 0, c.s));
+        HIP_TRY(launch_slab_copy(c.zeta_hist(), c.slab, h0 + sizeof(double) * cnt_h, (int64_t)row,
+                                 sizeof(double) * cnt_h, count, 0, c.s));
+        HIP_TRY(hipStreamSynchronize(c.s));
+        std::atomic_thread_fence(std::memory_order_acquire);
+        for (int32_t i = 0; i < count; ++i) {
+            const double* hr = reinterpret_cast<const double*>(reinterpret_cast<char*>(ctl) + row * i + sizeof(Ctrl));
+            if (err_hist) memcpy(err_hist + (size_t)i * hist_cap, hr, sizeof(double) * cnt_h);
+            if (zeta_hist) memcpy(zeta_hist + (size_t)i * hist_cap, hr + cnt_h, sizeof(double) * cnt_h);
         }
     }
     return first_err;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rpca {
 
 constexpr int KMAX = 16;          // largest rank / init block handled by the kernels
@@ -166,6 +168,18 @@ __device__ inline bool body_runs(const Ctrl* c, int body) {
 // (which completes every wave's stores at workgroup scope; the release fence
 // is cumulative over them) and before the barrier that hands the result to the
 // other waves. A fence in every wave multiplies the L2 write-backs.
+// p moved by off bytes (the data of another instance of a batched launch);
+// a null pointer stays null.
+template <typename X> __device__ inline X* shifted(X* p, int64_t off) {
+    return p ? reinterpret_cast<X*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)off) : p;
+}
+// The same for a pointer that is never null, as plain address arithmetic
+// (keeps a kernel argument in scalar registers).
+template <typename X> __device__ inline X* moved(X* p, int64_t off) {
+    using C = typename std::conditional<std::is_const<X>::value, const char, char>::type;
+    return reinterpret_cast<X*>(reinterpret_cast<C*>(p) + off);
+}
+
 __device__ inline bool last_block_arrives(uint32_t* counter, int* flag_smem) {
     __syncthreads();
     if (threadIdx.x == 0) {

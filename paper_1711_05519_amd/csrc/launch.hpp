@@ -25,6 +25,8 @@ struct StreamArgs {
     int32_t n_ct, n_rt;
     int32_t vec_ok;       // 1 if D rows are 16-byte aligned (vector loads allowed)
     int32_t body;         // Body: gating of the launch
+    int32_t batch;        // instances in the launch (grid y); every pointer above is
+    int64_t slab;         // instance 0's, instance i's lies i * slab bytes further
 };
 
 // Scalar geometry of the streaming pass (kernel argument; pointers are passed
@@ -32,6 +34,7 @@ struct StreamArgs {
 struct StreamGeom {
     int64_t ldd;
     int32_t m, n, TM, n_ct, n_rt, vec_ok, body;
+    int64_t slab;         // bytes between the instances of a batched launch (0: one instance)
 };
 
 struct MaterializeArgs {
@@ -78,6 +81,9 @@ struct PanelArgs {
     int32_t mode;             // kernel-specific
     int32_t body;             // Body of the gather kernel
     int32_t gated;            // basis kernel: skip when the body is not active
+    int32_t batch;            // instances in the launch (grid y), 0 or 1: one
+    int64_t slab;             // bytes between instances: every pointer but mlp and host_status
+                              // is instance 0's and is moved by blockIdx.y * slab
     int32_t lcorr;            // gather: the pass rebuilt L; add AL GBV to Y1 and BL GAU to Y2
 };
 
@@ -125,8 +131,10 @@ hipError_t launch_update(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_cross(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_basis(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_start(const PanelArgs& a, int K, int dtype, hipStream_t s);
-hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, hipStream_t s);
-hipError_t launch_enter_loop(Ctrl* ctrl, hipStream_t s);
+hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, int batch, int64_t slab, hipStream_t s);
+hipError_t launch_enter_loop(Ctrl* ctrl, int batch, int64_t slab, hipStream_t s);
+hipError_t launch_slab_copy(void* slab0, int64_t slab, void* flat, int64_t pitch, int64_t bytes, int count,
+                            int to_slabs, hipStream_t s);
 hipError_t launch_relax(const RelaxArgs& a, int dtype, hipStream_t s);
 
 // Reverse mode of unrolled relaxed iterations (adjoint.hip).

@@ -335,11 +335,50 @@ __device__ __forceinline__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const
 // the first of which holds the row): the per-tile partials of the
 // workgroup's rows are summed with 16-byte loads of whole tile blocks, then
 // the row products U_f^T Y1 (and Grams) are formed as workgroup partials.
+// Instance blockIdx.y of a batched launch: every pointer of the arguments
+// except the threshold network (shared) and the host status slot (unused in
+// batches) moves by blockIdx.y * slab bytes.
+__device__ inline PanelArgs at_instance(const PanelArgs& a0) {
+    PanelArgs a = a0;
+    if (a0.slab == 0) return a;
+    const int64_t off = (int64_t)blockIdx.y * a0.slab;
+    a.ctrl = shifted(a.ctrl, off);
+    a.small = shifted(a.small, off);
+    a.gpart = shifted(a.gpart, off);
+    a.P1 = shifted(a.P1, off);
+    a.P2 = shifted(a.P2, off);
+    a.resid = shifted(a.resid, off);
+    a.Y1 = shifted(a.Y1, off);
+    a.Y2 = shifted(a.Y2, off);
+    a.W1 = shifted(a.W1, off);
+    a.W2 = shifted(a.W2, off);
+    a.Ap = shifted(a.Ap, off);
+    a.Bp = shifted(a.Bp, off);
+    a.Unew = shifted(a.Unew, off);
+    a.Vnew = shifted(a.Vnew, off);
+    a.S2U = shifted(a.S2U, off);
+    a.S2V = shifted(a.S2V, off);
+    a.sigma_dst = shifted(a.sigma_dst, off);
+    a.Uf = shifted(a.Uf, off);
+    a.Vf = shifted(a.Vf, off);
+    a.AL = shifted(a.AL, off);
+    a.BL = shifted(a.BL, off);
+    a.srcU = shifted(a.srcU, off);
+    a.srcV = shifted(a.srcV, off);
+    a.src_sigma = shifted(a.src_sigma, off);
+    a.outU = shifted(a.outU, off);
+    a.outV = shifted(a.outV, off);
+    a.err_hist = shifted(a.err_hist, off);
+    a.zeta_hist = shifted(a.zeta_hist, off);
+    return a;
+}
+
 // The last workgroup sums the per-workgroup partials with all its threads.
 // FP32 (gram_form): also the Grams of Y1 and Y2, and the whole 2K x 2K step in
 // the tail. FP64: only C* and C2; the complement kernel forms W explicitly.
 template <typename T, int K>
-__global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
+__global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a_) {
+    PanelArgs a = at_instance(a_);
     using Acc = typename AccOf<T>::type;
     constexpr int RPB = GATHER_THREADS / GATHER_SPLIT;   // rows per workgroup
     constexpr bool GRAM = sizeof(T) == 4;
@@ -569,7 +608,8 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a) {
 // ---- kernel 2 (FP64): explicit complements W1, W2, their Grams, 2K x 2K step -
 
 template <typename T, int K>
-__global__ __launch_bounds__(PANEL_THREADS) void k_complement(PanelArgs a) {
+__global__ __launch_bounds__(PANEL_THREADS) void k_complement(PanelArgs a_) {
+    PanelArgs a = at_instance(a_);
     Ctrl* ctrl = a.ctrl;
     if (!ctrl->active) return;
     __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K];
@@ -625,7 +665,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_complement(PanelArgs a) {
 // Mode UPDATE_ENTER_EXACT keeps the FP64 trimmed factor and its Gram instead
 // (FP64 orthonormal bases for rpca_trim).
 template <typename T, int K>
-__global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
+__global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a_) {
+    PanelArgs a = at_instance(a_);
     Ctrl* ctrl = a.ctrl;
     const bool from_m = a.mode == UPDATE_FROM_M;
     if (a.body_id > 0 && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -771,7 +812,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a) {
 // For a rebuilding pass whose factors and bases were written elsewhere than by
 // the update kernel (which forms the same products itself).
 template <typename T, int K>
-__global__ __launch_bounds__(PANEL_THREADS) void k_cross(PanelArgs a) {
+__global__ __launch_bounds__(PANEL_THREADS) void k_cross(PanelArgs a_) {
+    PanelArgs a = at_instance(a_);
     Ctrl* ctrl = a.ctrl;
     __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K];
     __shared__ int flag;
@@ -805,7 +847,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_cross(PanelArgs a) {
 // (rpca_trim's output; inside the loop the update kernel folds this step.)
 
 template <typename T, int K>
-__global__ __launch_bounds__(PANEL_THREADS) void k_basis(PanelArgs a) {
+__global__ __launch_bounds__(PANEL_THREADS) void k_basis(PanelArgs a_) {
+    PanelArgs a = at_instance(a_);
     __shared__ double ri[K * K];
     const bool uside = (int)blockIdx.x < a.gU;
     block_load_small<K>(uside ? a.small->RAinv : a.small->RBinv, ri);
@@ -836,7 +879,8 @@ __device__ inline double hash_uniform(uint64_t seed, uint64_t idx) {
 }
 
 template <typename T, int K>
-__global__ __launch_bounds__(PANEL_THREADS) void k_start(PanelArgs a) {
+__global__ __launch_bounds__(PANEL_THREADS) void k_start(PanelArgs a_) {
+    PanelArgs a = at_instance(a_);
     Ctrl* ctrl = a.ctrl;
     __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K];
     __shared__ int flag;
@@ -869,18 +913,34 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_start(PanelArgs a) {
     if (lane_id() == 0) ctrl->cnt[CNT_START] = 0;
 }
 
-__global__ void k_setup(Ctrl* ctrl, Ctrl init) { if (threadIdx.x == 0 && blockIdx.x == 0) *ctrl = init; }
+__global__ void k_setup(Ctrl* ctrl, Ctrl init, int64_t slab) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *shifted(ctrl, (int64_t)blockIdx.y * slab) = init;
+}
 
 // The initialisation has converged and the entry update has run: switch the
 // control block to the loop (stopping rule on, k = 0) on the device.
-__global__ void k_enter_loop(Ctrl* ctrl) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+// (An instance of a batch whose initialisation failed keeps its state.)
+__global__ void k_enter_loop(Ctrl* ctrl_, int64_t slab) {
+    Ctrl* ctrl = shifted(ctrl_, (int64_t)blockIdx.y * slab);
+    if (threadIdx.x == 0 && blockIdx.x == 0 && ctrl->stage != STAGE_FAILED) {
         ctrl->stage = STAGE_MAIN;
         ctrl->want_stop = 1;
         ctrl->k = 0;
         ctrl->active = 1;
         ctrl->done = 0;
         ctrl->err_prev = 1e300;
+    }
+}
+
+// Copies `bytes` (a multiple of 4) between each instance of a batch (instance
+// blockIdx.x at slab0 + blockIdx.x * slab) and row blockIdx.x of a flat array
+// (pitch bytes apart): to_slabs 1 writes the instances, 0 reads them.
+__global__ void k_slab_copy(char* slab0, int64_t slab, char* flat, int64_t pitch, int64_t bytes, int to_slabs) {
+    uint32_t* a = reinterpret_cast<uint32_t*>(slab0 + (int64_t)blockIdx.x * slab);
+    uint32_t* b = reinterpret_cast<uint32_t*>(flat + (int64_t)blockIdx.x * pitch);
+    for (int64_t w = threadIdx.x; w < bytes / 4; w += blockDim.x) {
+        if (to_slabs) a[w] = b[w];
+        else b[w] = a[w];
     }
 }
 
@@ -908,7 +968,7 @@ __global__ void k_convert(const double* __restrict__ src, T* __restrict__ dst, i
 #define RPCA_LAUNCH_D(KK) hipLaunchKernelGGL((KFUN<double, KK>), grid, block, 0, s, a)
 #define RPCA_PANEL_LAUNCHER(NAME, GRID, BLOCK)                                                   \
     hipError_t NAME(const PanelArgs& a, int K, int dtype, hipStream_t s) {                       \
-        const dim3 grid(GRID), block(BLOCK);                                                     \
+        const dim3 grid(GRID, a.batch > 1 ? (unsigned)a.batch : 1u), block(BLOCK);              \
         if (dtype == 1) { RPCA_K_SWITCH(RPCA_LAUNCH_F) } else { RPCA_K_SWITCH(RPCA_LAUNCH_D) }   \
         return hipGetLastError();                                                                \
     }
@@ -935,13 +995,21 @@ RPCA_PANEL_LAUNCHER(launch_basis, (unsigned)(a.gU + a.gV), PANEL_THREADS)
 RPCA_PANEL_LAUNCHER(launch_start, (unsigned)(a.gU + a.gV), PANEL_THREADS)
 #undef KFUN
 
-hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, hipStream_t s) {
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, s, ctrl, init);
+hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, int batch, int64_t slab, hipStream_t s) {
+    hipLaunchKernelGGL(k_setup, dim3(1, batch > 1 ? (unsigned)batch : 1u), dim3(64), 0, s, ctrl, init, slab);
     return hipGetLastError();
 }
 
-hipError_t launch_enter_loop(Ctrl* ctrl, hipStream_t s) {
-    hipLaunchKernelGGL(k_enter_loop, dim3(1), dim3(64), 0, s, ctrl);
+hipError_t launch_enter_loop(Ctrl* ctrl, int batch, int64_t slab, hipStream_t s) {
+    hipLaunchKernelGGL(k_enter_loop, dim3(1, batch > 1 ? (unsigned)batch : 1u), dim3(64), 0, s, ctrl, slab);
+    return hipGetLastError();
+}
+
+hipError_t launch_slab_copy(void* slab0, int64_t slab, void* flat, int64_t pitch, int64_t bytes, int count,
+                            int to_slabs, hipStream_t s) {
+    if (count <= 0 || bytes <= 0 || (bytes & 3) || (pitch & 3) || (slab & 3)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_slab_copy, dim3((unsigned)count), dim3(256), 0, s, static_cast<char*>(slab0), slab,
+                       static_cast<char*>(flat), pitch, bytes, to_slabs);
     return hipGetLastError();
 }
 

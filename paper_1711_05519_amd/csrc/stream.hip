@@ -283,6 +283,18 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream(
     const T* __restrict__ Vf, typename AccOf<T>::type* __restrict__ P1, typename AccOf<T>::type* __restrict__ P2,
     double* __restrict__ resid, const Ctrl* __restrict__ ctrl, StreamGeom g) {
     using Acc = typename AccOf<T>::type;
+    {   // instance blockIdx.y of a batched launch (slab 0: a single instance)
+        const int64_t off = (int64_t)blockIdx.y * g.slab;
+        D = moved(D, off);
+        AL = moved(AL, off);
+        BL = moved(BL, off);
+        Uf = moved(Uf, off);
+        Vf = moved(Vf, off);
+        P1 = moved(P1, off);
+        P2 = moved(P2, off);
+        resid = moved(resid, off);
+        ctrl = moved(ctrl, off);
+    }
     if (!body_runs(ctrl, g.body)) return;
     const T zeta = static_cast<T>(ctrl->zeta);
 
@@ -400,8 +412,9 @@ __global__ __launch_bounds__(256) void k_read_probe(const float4* __restrict__ p
 template <typename T, bool REBUILD>
 hipError_t stream_dispatch(const StreamArgs& a, int K, hipStream_t s) {
     using Acc = typename AccOf<T>::type;
-    const dim3 grid((unsigned)(a.n_ct * a.n_rt)), block(STREAM_THREADS);
+    const dim3 grid((unsigned)(a.n_ct * a.n_rt), a.batch > 1 ? (unsigned)a.batch : 1u), block(STREAM_THREADS);
     StreamGeom geom;
+    geom.slab = a.batch > 1 ? a.slab : 0;
     geom.ldd = a.ldd;
     geom.m = a.m;
     geom.n = a.n;

@@ -217,6 +217,18 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream_mx(
     const float* __restrict__ Uf, const float* __restrict__ Vf, float* __restrict__ P1, float* __restrict__ P2,
     double* __restrict__ resid, const Ctrl* __restrict__ ctrl, StreamGeom g) {
     static_assert(K <= 16, "MFMA N = 16 holds up to 16 columns");
+    {   // instance blockIdx.y of a batched launch (slab 0: a single instance)
+        const int64_t off = (int64_t)blockIdx.y * g.slab;
+        D = moved(D, off);
+        AL = moved(AL, off);
+        BL = moved(BL, off);
+        Uf = moved(Uf, off);
+        Vf = moved(Vf, off);
+        P1 = moved(P1, off);
+        P2 = moved(P2, off);
+        resid = moved(resid, off);
+        ctrl = moved(ctrl, off);
+    }
     if (!body_runs(ctrl, g.body)) return;
     const float zeta = static_cast<float>(ctrl->zeta);
     const int lane = threadIdx.x & (WAVE - 1);
@@ -295,8 +307,9 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream_mx(
 
 template <bool REBUILD>
 hipError_t mx_dispatch(const StreamArgs& a, int K, hipStream_t s) {
-    const dim3 grid((unsigned)(a.n_ct * a.n_rt)), block(STREAM_THREADS);
+    const dim3 grid((unsigned)(a.n_ct * a.n_rt), a.batch > 1 ? (unsigned)a.batch : 1u), block(STREAM_THREADS);
     StreamGeom geom;
+    geom.slab = a.batch > 1 ? a.slab : 0;
     geom.ldd = a.ldd;
     geom.m = a.m;
     geom.n = a.n;

@@ -17,7 +17,9 @@ library's solver; the comparison systems are not part of this package).
   python -m paper_1711_05519_amd.experiments many [--count 32]
       Throughput on many small problems (the instance pool of the learned
       threshold: 2000 x 2000, r = 5 .. 10, alpha 0.05 .. 0.3, FP32): solves
-      one after another against rpca_solve_many on 4, 8 and 16 streams.
+      one after another against rpca_solve_many on 4, 8 and 16 streams and
+      against rpca_solve_batch (one batch per rank, every launch covering
+      all instances of the batch).
   python -m paper_1711_05519_amd.experiments video
       Video-shaped workload (144 x 176 pixels x 2000 frames, r = 2, the
       stand-in for the background-subtraction data): time, iterations and the
@@ -158,6 +160,31 @@ def many(args):
         emit(experiment="many", mode=f"{ns} streams", count=args.count, seconds=t, per_solve=t / args.count,
              iterations=sum(i.iterations for i in infos), speedup=t_seq / t,
              same_iterations=[i.iterations for i in infos] == its)
+    # batched: one rpca_solve_batch per rank r (every kernel launch covers the
+    # instances of that rank); D is copied into the slabs before timing
+    groups = {}
+    for i, x in enumerate(xs):
+        groups.setdefault(x.r, []).append(i)
+    batches = []
+    for r, idx in sorted(groups.items()):
+        gx = [xs[i] for i in idx]
+        bs = R.BatchSolver(torch.stack([Ds[i] for i in idx]), r, [x.beta for x in gx], [x.beta_init for x in gx],
+                           [x.gamma for x in gx], [x.mu_in for x in gx], tol=[x.tol for x in gx], seed=1)
+        batches.append((idx, bs))
+    for _, bs in batches:   # warm-up
+        bs.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [(idx, bs.solve()) for idx, bs in batches]
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    its_b = [0] * args.count
+    for idx, infos in res:
+        for i, info in zip(idx, infos):
+            its_b[i] = info.iterations
+    emit(experiment="many", mode=f"batched ({len(batches)} batches, one per rank)", count=args.count,
+         seconds=t, per_solve=t / args.count, iterations=sum(its_b), speedup=t_seq / t, same_iterations=its_b == its,
+         bytes_of_D=args.count * xs[0].m * xs[0].n * 4)
 
 
 def video(args):

@@ -38,7 +38,8 @@ EXPORTED = ("rpca_workspace_size", "rpca_init", "rpca_trim", "rpca_step", "rpca_
             "rpca_solve_many",
             "rpca_materialize", "rpca_tangent_products", "rpca_strerror",
             "rpca_last_hip_error", "rpca_version", "rpca_profile_enable", "rpca_profile_read",
-            "rpca_relaxed_step", "rpca_unrolled_adjoint", "rpca_mlp_forward", "rpca_mlp_backward", "rpca_mlp_adam", "rpca_read_probe")
+            "rpca_relaxed_step", "rpca_unrolled_adjoint", "rpca_batch_layout_of", "rpca_solve_batch",
+            "rpca_mlp_forward", "rpca_mlp_backward", "rpca_mlp_adam", "rpca_read_probe")
 
 
 class RpcaError(RuntimeError):
@@ -66,6 +67,11 @@ class State(ctypes.Structure):
                 ("sigma1_pt", ctypes.c_double), ("sigma_r1_pt", ctypes.c_double),
                 ("normD", ctypes.c_double), ("k", ctypes.c_int32), ("init_passes", ctypes.c_int32),
                 ("svd_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchLayout(ctypes.Structure):
+    _fields_ = [("slab_bytes", ctypes.c_size_t), ("off_D", ctypes.c_size_t), ("off_U", ctypes.c_size_t),
+                ("off_V", ctypes.c_size_t), ("off_sigma", ctypes.c_size_t), ("off_ws", ctypes.c_size_t)]
 
 
 class RelaxResult(ctypes.Structure):
@@ -99,6 +105,8 @@ def _lib():
             "rpca_materialize": [vp, P, S, vp, ctypes.c_int64, vp, ctypes.c_int64, vp, sz, vp],
             "rpca_tangent_products": [vp, P, vp, vp, d, vp, vp, vp, vp, pd, vp, sz, vp],
             "rpca_relaxed_step": [vp, P, S, d, d, vp, vp, ctypes.c_int32, ctypes.POINTER(RelaxResult), vp, sz, vp],
+            "rpca_batch_layout_of": [P, ctypes.POINTER(BatchLayout)],
+            "rpca_solve_batch": [ctypes.c_int32, vp, P, S, pd, pd, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp],
             "rpca_unrolled_adjoint": [vp, P, ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       pd, pd, pd, vp, vp, ctypes.c_int32, pd, vp, vp, vp, vp, sz, vp],
             "rpca_mlp_forward": [vp, vp, ctypes.c_int32, vp, vp],
@@ -380,6 +388,82 @@ def make_params(D: torch.Tensor, r: int, beta: float, beta_init: float, gamma: f
                          | (RPCA_FLAG_TRAINING if training else 0) | (RPCA_FLAG_LEARNED if learned is not None else 0)),
                   seed=int(seed), mixed_err=float(mixed_err),
                   zeta_mlp=(_f32(learned, RPCA_MLP_PARAMS) if learned is not None else None))
+
+
+RPCA_BATCH_MAX = 65535
+
+
+class BatchSolver:
+    """Many instances of one shape solved together (rpca_solve_batch): every
+    kernel launch covers all of them. Owns one device slab per instance
+    (its D, its iterate and its workspace, rpca_batch_layout_of)."""
+
+    def __init__(self, D: torch.Tensor, r: int, beta, beta_init, gamma, mu, tol=1e-5, max_iter: int = 100,
+                 trim: bool = True, init_block: int = 0, init_max_passes: int = 0, seed: int = 0,
+                 mixed: bool = False, learned: torch.Tensor | None = None):
+        """D: (count, m, n) device tensor (float32 or float64); copied into the
+        slabs. beta, beta_init, gamma, mu, tol: one value for all instances or
+        one per instance."""
+        if not D.is_cuda or D.dim() != 3:
+            raise ValueError("D must be a (count, m, n) device tensor")
+        count, m, n = D.shape
+        if not 1 <= count <= RPCA_BATCH_MAX:
+            raise ValueError("1 <= count <= RPCA_BATCH_MAX")
+        self.count = count
+
+        def each(v):
+            v = list(v) if isinstance(v, (list, tuple, np.ndarray)) else [v] * count
+            if len(v) != count:
+                raise ValueError("one value or one per instance")
+            return [float(x) for x in v]
+
+        b, bi, g, mu_, tl = each(beta), each(beta_init), each(gamma), each(mu), each(tol)
+        self.params_all = (Params * count)()
+        for i in range(count):
+            self.params_all[i] = make_params(D[0], r, b[i], bi[i], g[i], mu_[i], tl[i], max_iter, trim, init_block,
+                                             init_max_passes, seed, mixed, 0.0, False, learned)
+            self.params_all[i].ldd = n
+        self.params = self.params_all[0]
+        self._learned = learned
+        lay = BatchLayout()
+        _check(_lib().rpca_batch_layout_of(ctypes.byref(self.params), ctypes.byref(lay)), "rpca_batch_layout_of")
+        self.layout = lay
+        sb = lay.slab_bytes
+        raw = torch.empty(count * sb + 256, dtype=torch.uint8, device=D.device)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.slabs = raw[off:off + count * sb].view(count, sb)
+        esz = D.element_size()
+
+        def region(o, nbytes, dtype, shape):
+            return self.slabs[:, o:o + nbytes].view(dtype).view((count,) + shape)
+
+        self.D = region(lay.off_D, m * n * esz, D.dtype, (m, n))
+        self.U = region(lay.off_U, m * r * 8, torch.float64, (m, r))
+        self.V = region(lay.off_V, n * r * 8, torch.float64, (n, r))
+        self.sigma = region(lay.off_sigma, r * 8, torch.float64, (r,))
+        self.D.copy_(D)
+
+    def solve(self):
+        """Solves every instance; returns their SolveInfo (status per instance)."""
+        n = self.count
+        cap = self.params.max_iter + 1
+        eh = (ctypes.c_double * (n * cap))()
+        zh = (ctypes.c_double * (n * cap))()
+        st = (State * n)()
+        status = (ctypes.c_int32 * n)()
+        torch.cuda.current_stream(self.D.device).synchronize()
+        rc = _lib().rpca_solve_batch(n, ctypes.c_void_p(self.slabs.data_ptr()), self.params_all, st,
+                                     eh, zh, cap, status, _stream(None))
+        if rc < 0 and all(s >= 0 for s in status[:n]):
+            _check(rc, "rpca_solve_batch")
+        out = []
+        for i in range(n):
+            k = st[i].k
+            out.append(SolveInfo(status=status[i], iterations=k, err=st[i].err, zeta=st[i].zeta,
+                                 err_hist=list(eh[i * cap:i * cap + k + 1]), zeta_hist=list(zh[i * cap:i * cap + k + 1]),
+                                 init_passes=st[i].init_passes, svd_sweeps=st[i].svd_sweeps))
+        return out
 
 
 class Solver:

@@ -1,0 +1,157 @@
+"""Batched solve (rpca_solve_batch: every kernel launch covers all instances)
+against the FP64 oracle instance by instance, against the same instances
+solved one at a time (FP32, mixed and learned forms), with failing instances
+inside a batch, and at the scale of the training pool (64 instances of
+2000 x 2000) against the ground truth."""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1711_05519_amd import inputs as I
+from paper_1711_05519_amd import learn as LN
+from paper_1711_05519_amd import rpca as R
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def L_of(U, s, V):
+    U, s, V = (np.asarray(t.cpu().numpy() if isinstance(t, torch.Tensor) else t, np.float64) for t in (U, s, V))
+    return (U * s) @ V.T
+
+
+def draw(m, n, r, alpha, seeds, tol):
+    xs = [I.gaussian_instance(m, n, r, alpha, 1.0, seed=s, tol=tol) for s in seeds]
+    return xs, xs[0]   # the batch shares the parameters of the first instance
+
+
+def batch_of(xs, p, dtype, **kw):
+    D = torch.stack([torch.as_tensor(x.D, dtype=dtype) for x in xs]).cuda()
+    return R.BatchSolver(D, p.r, p.beta, p.beta_init, p.gamma, p.mu_in, tol=p.tol, seed=7, **kw)
+
+
+def single(x, p, dtype, **kw):
+    D = torch.as_tensor(x.D, dtype=dtype, device="cuda")
+    sv = R.Solver(D, p.r, p.beta, p.beta_init, p.gamma, p.mu_in, tol=p.tol, seed=7, **kw)
+    return sv, sv.solve()
+
+
+def test_batch_fp64_against_oracle():
+    xs, p = draw(240, 300, 3, 0.1, [21, 22, 23, 24], 1e-7)
+    bs = batch_of(xs, p, torch.float64)
+    infos = bs.solve()
+    op = O.Params(r=p.r, beta=p.beta, beta_init=p.beta_init, gamma=p.gamma, mu=p.mu_in, tol=p.tol)
+    for i, (x, info) in enumerate(zip(xs, infos)):
+        ref = O.solve(x.D, op)
+        L = L_of(bs.U[i], bs.sigma[i], bs.V[i])
+        d = rel(L, ref.state.L())
+        say(f"instance {i}: {info.iterations}/{ref.iterations} iterations, rel L to oracle {d:.2e}")
+        assert info.status == R.RPCA_OK
+        assert info.iterations == ref.iterations
+        np.testing.assert_allclose(info.err_hist, ref.err_hist, rtol=1e-8)
+        # zeta_{k+1} = beta (sigma_{r+1} + gamma^{k+1} sigma_1): sigma_{r+1} falls to the
+        # rounding level of the 2r x 2r SVD late in a solve, where it is resolved only to
+        # about 1e-8 sigma_1 (beta sigma_1 <= zeta_1 / gamma)
+        np.testing.assert_allclose(info.zeta_hist, ref.zeta_hist, rtol=1e-10,
+                                   atol=2e-8 * ref.zeta_hist[1] / p.gamma)
+        assert d <= 1e-10
+        assert O.recovery_error(L, x.L) <= 1e-4
+
+
+@pytest.mark.parametrize("form", ["plain", "mixed", "learned"])
+def test_batch_matches_single_solves_fp32(form):
+    kw = {}
+    if form == "mixed":
+        kw["mixed"] = True
+    if form == "learned":
+        kw["learned"] = LN.load_theta(os.path.join(os.path.dirname(LN.__file__), "zeta_mlp.npy"))
+    xs, p = draw(500, 420, 4, 0.15, [31, 32, 33, 34, 35, 36], 1e-5)
+    bs = batch_of(xs, p, torch.float32, **kw)
+    infos = bs.solve()
+    for i, (x, info) in enumerate(zip(xs, infos)):
+        sv, ref = single(x, p, torch.float32, **kw)
+        L = L_of(bs.U[i], bs.sigma[i], bs.V[i])
+        d = rel(L, L_of(sv.U, sv.sigma, sv.V))
+        say(f"{form} instance {i}: {info.iterations}/{ref.iterations} iterations, rel L to the single solve {d:.2e}")
+        assert info.status == ref.status == R.RPCA_OK
+        assert info.iterations == ref.iterations and info.init_passes == ref.init_passes
+        # the batch tiles each instance differently (fewer row tiles): FP32 sums in another order
+        np.testing.assert_allclose(info.err_hist, ref.err_hist, rtol=1e-3)
+        assert d <= 1e-5
+        assert O.recovery_error(L, x.L) <= 1e-4
+
+
+def test_batch_isolates_failing_instances():
+    xs, p = draw(200, 180, 2, 0.1, [41, 42, 43, 44], 1e-5)
+    D = torch.stack([torch.as_tensor(x.D, dtype=torch.float32) for x in xs])
+    D[1, 17, 33] = float("nan")
+    D[2].zero_()
+    bs = R.BatchSolver(D.cuda(), p.r, p.beta, p.beta_init, p.gamma, p.mu_in, tol=p.tol, seed=7)
+    infos = bs.solve()
+    assert [i.status for i in infos] == [R.RPCA_OK, R.RPCA_EINVAL, R.RPCA_EINVAL, R.RPCA_OK]
+    for i in (0, 3):
+        sv, ref = single(xs[i], p, torch.float32)
+        assert infos[i].iterations == ref.iterations
+        assert rel(L_of(bs.U[i], bs.sigma[i], bs.V[i]), L_of(sv.U, sv.sigma, sv.V)) <= 1e-5
+
+
+def test_batch_rejects_mixed_with_a_switching_level():
+    xs, p = draw(100, 90, 2, 0.1, [51, 52], 1e-5)
+    D = torch.stack([torch.as_tensor(x.D, dtype=torch.float32) for x in xs]).cuda()
+    bs = R.BatchSolver(D, p.r, p.beta, p.beta_init, p.gamma, p.mu_in, tol=p.tol, mixed=True)
+    for q in bs.params_all:
+        q.mixed_err = 1e-3       # a batch takes BF16 products in every body or in none
+    assert [i.status for i in bs.solve()] == [R.RPCA_EINVAL, R.RPCA_EINVAL]
+
+
+def test_batch_training_pool_scale():
+    """The first 64 instances of the 2000 x 2000 training pool, FP32, one batch
+    per rank r (5..10; each instance with its own beta, mu, ...): every one
+    recovers L = P Q^T (Section 3's bar 1e-4), and one per batch matches its
+    single solve."""
+    t0 = time.perf_counter()
+    xs = [I.config_instance(5, i, keep_L=False) for i in range(64)]
+    say(f"64 instances drawn in {time.perf_counter() - t0:.1f} s")
+    worst, t_all = 0.0, 0.0
+    for r in sorted(set(x.r for x in xs)):
+        grp = [x for x in xs if x.r == r]
+        D = torch.stack([torch.as_tensor(x.D, dtype=torch.float32) for x in grp]).cuda()
+        bs = R.BatchSolver(D, r, [x.beta for x in grp], [x.beta_init for x in grp], [x.gamma for x in grp],
+                           [x.mu_in for x in grp], tol=[x.tol for x in grp], seed=7)
+        del D
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = bs.solve()
+        dt = time.perf_counter() - t0
+        t_all += dt
+        for i, (x, info) in enumerate(zip(grp, infos)):
+            assert info.status == R.RPCA_OK
+            U, s_, V = bs.U[i], bs.sigma[i], bs.V[i]
+            P = torch.as_tensor(x.P, dtype=torch.float64, device="cuda")
+            Q = torch.as_tensor(x.Q, dtype=torch.float64, device="cuda")
+            a = ((U * s_).T @ (U * s_)) * (V.T @ V)
+            b = (P.T @ P) * (Q.T @ Q)
+            c = ((U * s_).T @ P) * (V.T @ Q)
+            worst = max(worst, float(torch.sqrt(torch.clamp(a.sum() + b.sum() - 2 * c.sum(), min=0) / b.sum())))
+        say(f"r={r}: {len(grp)} instances in {dt * 1e3:.1f} ms, iterations {sorted(set(i.iterations for i in infos))}")
+        x = grp[-1]
+        sv, ref = single(x, x, torch.float32)
+        assert infos[-1].iterations == ref.iterations
+        assert rel(L_of(bs.U[-1], bs.sigma[-1], bs.V[-1]), L_of(sv.U, sv.sigma, sv.V)) <= 1e-5
+        for x in grp:
+            x.D = None
+    say(f"64 instances: {t_all * 1e3:.1f} ms in batches by rank, worst recovery error {worst:.2e}")
+    assert worst <= 1e-4
