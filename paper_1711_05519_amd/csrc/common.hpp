@@ -168,6 +168,18 @@ __device__ inline bool body_runs(const Ctrl* c, int body) {
 // (which completes every wave's stores at workgroup scope; the release fence
 // is cumulative over them) and before the barrier that hands the result to the
 // other waves. A fence in every wave multiplies the L2 write-backs.
+// Tile handled by workgroup b of a G-workgroup launch. Workgroups are handed to
+// the 8 XCDs of the device in turn (b, b + 8, ... on XCD b % 8); numbering the
+// tiles so that each XCD takes one contiguous run puts neighbouring tiles
+// (the column tiles of a row band, which share the cache lines at their
+// edges) on one XCD and its L2. A bijection of 0..G-1.
+__device__ inline int xcd_tile(int b, int G) {
+    constexpr int NX = 8;
+    const int q = G / NX, rm = G % NX;
+    const int x = b % NX, pos = b / NX;
+    return (x < rm ? x * (q + 1) : rm * (q + 1) + (x - rm) * q) + pos;
+}
+
 // p moved by off bytes (the data of another instance of a batched launch);
 // a null pointer stays null.
 template <typename X> __device__ inline X* shifted(X* p, int64_t off) {

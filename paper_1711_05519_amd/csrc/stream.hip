@@ -300,8 +300,9 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream(
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const int ct = blockIdx.x % g.n_ct;
-    const int rt = blockIdx.x / g.n_ct;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int ct = tile % g.n_ct;
+    const int rt = tile / g.n_ct;
     const int jb = ct * STREAM_TN + lane * STREAM_CPL;
     const int nvalid = min(max(g.n - jb, 0), STREAM_CPL);
 
@@ -350,7 +351,7 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream(
         if (col < g.n) P2[((size_t)rt * g.n + col) * K + (idx % K)] = sm[idx];
     }
     const double rtot = block_sum_256(res, red);
-    if (threadIdx.x == 0) resid[blockIdx.x] = rtot;
+    if (threadIdx.x == 0) resid[tile] = rtot;
     if constexpr (!REBUILD) {
         // max |D_ij| over the tile, behind the residuals of all tiles
         double v = static_cast<double>(amax);
@@ -360,7 +361,7 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream(
         if (threadIdx.x == 0) {
             double mx = red[0];
             for (int w = 1; w < STREAM_WAVES; ++w) mx = fmax(mx, red[w]);
-            resid[gridDim.x + blockIdx.x] = mx;
+            resid[gridDim.x + tile] = mx;
         }
     }
 }
