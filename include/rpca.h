@@ -24,6 +24,12 @@
  * - stream is a hipStream_t (0 = the null stream). Every device operation is
  *   ordered on it. Calls that report host-visible results (the scalars of
  *   rpca_state, histories) synchronise with the stream before returning.
+ * - Tracing: with the environment variable RPCA_TRACE set to "1" (stderr) or
+ *   to a file name (appended), rpca_solve and rpca_solve_batch write, after
+ *   the device work, one JSON line per state k of each solve (err_k, zeta_k;
+ *   for a batch when histories are requested) and a summary line (status,
+ *   iterations, initialisation passes, sigma_1 and sigma_{r+1} of the last
+ *   P_T(D - S_k), shape, flags). Unset or "0": nothing is written.
  * - One call at a time per workspace; calls sharing a workspace must not
  *   overlap. Calls with distinct workspaces may run concurrently; at most 32
  *   rpca_init / rpca_solve calls may be in flight per device (each holds a

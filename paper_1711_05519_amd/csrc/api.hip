@@ -11,6 +11,8 @@
 // into mapped host memory, one body late; bodies queued past the stop become
 // no-ops on the device (Ctrl gating), so the GPU never waits for the host.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <atomic>
@@ -809,6 +811,35 @@ int rpca_init(const void* D, const rpca_params* p, rpca_state* st, void* ws, siz
     return RPCA_OK;
 }
 
+// RPCA_TRACE: unset or "0" off; "1" JSON lines on stderr; anything else is a
+// file that the lines are appended to. One line per state k of a finished solve
+// (err_k, zeta_k) and a summary line; written after the device work is done.
+std::mutex g_trace_mutex;
+
+void trace_solve(const char* call, int instance, int status, const Ctrl& fin, const double* err, const double* zeta,
+                 int cnt, const rpca_params* p) {
+    const char* where = getenv("RPCA_TRACE");
+    if (!where || !*where || strcmp(where, "0") == 0) return;
+    std::lock_guard<std::mutex> lock(g_trace_mutex);
+    FILE* f = strcmp(where, "1") == 0 ? stderr : fopen(where, "a");
+    if (!f) return;
+    for (int k = 0; err && zeta && k < cnt; ++k)
+        fprintf(f, "{\"call\": \"%s\", \"instance\": %d, \"k\": %d, \"err\": %.17g, \"zeta\": %.17g}\n", call,
+                instance, k, err[k], zeta[k]);
+    fprintf(f,
+            "{\"call\": \"%s\", \"instance\": %d, \"status\": %d, \"iterations\": %d, \"init_passes\": %d, "
+            "\"err\": %.17g, \"zeta\": %.17g, \"sigma1\": %.17g, \"sigma_r1\": %.17g, \"m\": %lld, \"n\": %lld, "
+            "\"r\": %d, \"dtype\": \"%s\", \"flags\": %u}\n",
+            call, instance, status, fin.k, fin.total_passes, fin.err, fin.zeta, fin.sig1_pt, fin.sigr1_pt,
+            (long long)p->m, (long long)p->n, p->r, p->dtype == RPCA_F32 ? "f32" : "f64", p->flags);
+    if (f != stderr) fclose(f);
+}
+
+bool trace_on() {
+    const char* where = getenv("RPCA_TRACE");
+    return where && *where && strcmp(where, "0") != 0;
+}
+
 // One solve (Algorithm 3, then Algorithm 1) as a queue of bodies that the host
 // advances step by step, so that several solves can share one host thread.
 // Bodies are queued one ahead of the host: initialisation bodies until a
@@ -912,7 +943,15 @@ public:
         if (cnt > 0 && zeta_hist_)
             HIP_TRY(hipMemcpyAsync(zeta_hist_, c_.zeta_hist(), sizeof(double) * cnt, hipMemcpyDeviceToHost, c_.s));
         HIP_TRY(hipStreamSynchronize(c_.s));
-        return fin.stopped_by_tol ? RPCA_OK : RPCA_MAXITER;
+        const int status = fin.stopped_by_tol ? RPCA_OK : RPCA_MAXITER;
+        if (trace_on()) {
+            std::vector<double> eh((size_t)n), zh((size_t)n);
+            HIP_TRY(hipMemcpyAsync(eh.data(), c_.err_hist(), sizeof(double) * n, hipMemcpyDeviceToHost, c_.s));
+            HIP_TRY(hipMemcpyAsync(zh.data(), c_.zeta_hist(), sizeof(double) * n, hipMemcpyDeviceToHost, c_.s));
+            HIP_TRY(hipStreamSynchronize(c_.s));
+            trace_solve("rpca_solve", 0, status, fin, eh.data(), zh.data(), n, p_);
+        }
+        return status;
     }
 
 private:
@@ -1224,6 +1263,15 @@ int rpca_solve_batch(int32_t count, void* slabs, const rpca_params* params, rpca
             const double* hr = reinterpret_cast<const double*>(reinterpret_cast<char*>(ctl) + row * i + sizeof(Ctrl));
             if (err_hist) memcpy(err_hist + (size_t)i * hist_cap, hr, sizeof(double) * cnt_h);
             if (zeta_hist) memcpy(zeta_hist + (size_t)i * hist_cap, hr + cnt_h, sizeof(double) * cnt_h);
+        }
+    }
+    if (trace_on()) {
+        const bool h = cnt_h > 0 && (err_hist || zeta_hist);
+        for (int32_t i = 0; i < count; ++i) {
+            const double* hr = reinterpret_cast<const double*>(reinterpret_cast<char*>(ctl) + row * i + sizeof(Ctrl));
+            const int n = at(i).k + 1 < cnt_h ? at(i).k + 1 : cnt_h;
+            trace_solve("rpca_solve_batch", i, status[i], at(i), h ? hr : nullptr, h ? hr + cnt_h : nullptr, n,
+                        &params[i]);
         }
     }
     return first_err;
