@@ -233,7 +233,8 @@ int rpca_solve_many(int32_t count, const void *const *D, const rpca_params *cons
  * instance i, may be NULL) entries 0..st[i].k; status[i] the status
  * rpca_solve would return. Returns RPCA_OK or the first negative instance
  * status; RPCA_EINVAL for bad arguments (1 <= count <= RPCA_BATCH_MAX). Returns
- * after the device work is done. */
+ * after the device work is done. Batched calls on one device run one at a time
+ * (they share a small buffer of mapped host memory that the library keeps). */
 typedef struct rpca_batch_layout {
     size_t slab_bytes;               /* bytes per instance (a multiple of 256)         */
     size_t off_D, off_U, off_V, off_sigma, off_ws;   /* offsets inside a slab          */

@@ -65,6 +65,12 @@ struct DeviceInfo {
     HostStatus* status_dev = nullptr;
     uint32_t slots_used = 0;             // bit i: slot i belongs to a call (g_dev_mutex)
     void* scratch = nullptr;             // this device's copy of `scratch` (rpca_step_noalloc)
+    // mapped host buffer of rpca_solve_batch, grown on demand and kept; one
+    // batched call at a time per device holds batch_mutex while it uses it
+    std::mutex batch_mutex;
+    void* batch_host = nullptr;
+    void* batch_dev = nullptr;
+    size_t batch_bytes = 0;
 };
 std::mutex g_dev_mutex;
 DeviceInfo g_dev[MAX_DEVICES];
@@ -1124,29 +1130,29 @@ int rpca_batch_layout_of(const rpca_params* p, rpca_batch_layout* out) {
 // and reads all control blocks in between (one strided copy).
 static_assert(sizeof(Ctrl) % 8 == 0, "control blocks are copied in 4-byte words, rows stay 8-byte aligned");
 
-// Mapped, coherent host memory for one call (device view through dev()).
-class MappedBuffer {
-public:
-    explicit MappedBuffer(size_t bytes) {
-        if (hipHostMalloc(&h_, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
-            h_ = nullptr;
-            return;
-        }
-        if (hipHostGetDevicePointer(&d_, h_, 0) != hipSuccess) d_ = nullptr;
+// The device's mapped, coherent host buffer for batched calls, at least
+// `bytes` long (batch_mutex held by the caller). Returns false if it cannot be
+// allocated.
+bool batch_buffer(DeviceInfo* d, size_t bytes) {
+    if (d->batch_bytes >= bytes) return true;
+    if (d->batch_host) {
+        (void)hipHostFree(d->batch_host);
+        d->batch_host = d->batch_dev = nullptr;
+        d->batch_bytes = 0;
     }
-    ~MappedBuffer() {
-        if (h_) (void)hipHostFree(h_);
+    void* h = nullptr;
+    const size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
+    if (hipHostMalloc(&h, want, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return false;
+    void* dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, h, 0) != hipSuccess) {
+        (void)hipHostFree(h);
+        return false;
     }
-    MappedBuffer(const MappedBuffer&) = delete;
-    MappedBuffer& operator=(const MappedBuffer&) = delete;
-    bool ok() const { return h_ && d_; }
-    void* host() const { return h_; }
-    void* dev() const { return d_; }
-
-private:
-    void* h_ = nullptr;
-    void* d_ = nullptr;
-};
+    d->batch_host = h;
+    d->batch_dev = dp;
+    d->batch_bytes = want;
+    return true;
+}
 
 // Fields that every instance of a batch must share (one launch shape).
 bool same_shape(const rpca_params* a, const rpca_params* b) {
@@ -1184,15 +1190,20 @@ int rpca_solve_batch(int32_t count, void* slabs, const rpca_params* params, rpca
     // kernel (one row per instance)
     const int cnt_h = hist_cap < p->max_iter + 1 ? hist_cap : p->max_iter + 1;
     const size_t row = sizeof(Ctrl) + 2 * sizeof(double) * (size_t)(cnt_h > 0 ? cnt_h : 0);
-    MappedBuffer hb(row * (size_t)count);
-    if (!hb.ok()) {
+    std::lock_guard<std::mutex> hold(c.dev->batch_mutex);
+    if (!batch_buffer(c.dev, row * (size_t)count)) {
         g_last_hip_error = (int)hipErrorOutOfMemory;
         return RPCA_EHIP;
     }
-    Ctrl* ctl = reinterpret_cast<Ctrl*>(hb.host());
+    void* const hb_dev = c.dev->batch_dev;
+    Ctrl* ctl = reinterpret_cast<Ctrl*>(c.dev->batch_host);
+    // (the host spins on the stream instead of a blocking wait, which can put
+    // the thread to sleep for much longer than a few bodies take)
     auto read_all = [&]() -> int {
-        HIP_TRY(launch_slab_copy(c.ctrl(), c.slab, hb.dev(), (int64_t)row, sizeof(Ctrl), count, 0, c.s));
-        HIP_TRY(hipStreamSynchronize(c.s));
+        HIP_TRY(launch_slab_copy(c.ctrl(), c.slab, hb_dev, (int64_t)row, sizeof(Ctrl), count, 0, c.s));
+        hipError_t q;
+        while ((q = hipStreamQuery(c.s)) == hipErrorNotReady) cpu_relax();
+        HIP_TRY(q);
         std::atomic_thread_fence(std::memory_order_acquire);
         return RPCA_OK;
     };
@@ -1203,7 +1214,7 @@ int rpca_solve_batch(int32_t count, void* slabs, const rpca_params* params, rpca
     const Ctrl t = base_ctrl(c, STAGE_SIGMA_D, INFINITY, 0, 1.0, 0);
     for (int32_t i = 0; i < count; ++i) at(i) = base_ctrl(c, STAGE_SIGMA_D, INFINITY, 0, 1.0, 0, &params[i]);
     std::atomic_thread_fence(std::memory_order_release);
-    HIP_TRY(launch_slab_copy(c.ctrl(), c.slab, hb.dev(), (int64_t)row, sizeof(Ctrl), count, 1, c.s));
+    HIP_TRY(launch_slab_copy(c.ctrl(), c.slab, hb_dev, (int64_t)row, sizeof(Ctrl), count, 1, c.s));
     HIP_TRY(hipStreamSynchronize(c.s));
     PanelArgs sa = panel_args(c);
     sa.seed = p->seed;
@@ -1253,7 +1264,7 @@ int rpca_solve_batch(int32_t count, void* slabs, const rpca_params* params, rpca
     }
     if (cnt_h > 0 && (err_hist || zeta_hist)) {
         // err and zeta histories are adjacent in the workspace: one row each
-        char* h0 = static_cast<char*>(hb.dev()) + sizeof(Ctrl);
+        char* h0 = static_cast<char*>(hb_dev) + sizeof(Ctrl);
         HIP_TRY(launch_slab_copy(c.err_hist(), c.slab, h0, (int64_t)row, sizeof(double) * cnt_h, count, 0, c.s));
         HIP_TRY(launch_slab_copy(c.zeta_hist(), c.slab, h0 + sizeof(double) * cnt_h, (int64_t)row,
                                  sizeof(double) * cnt_h, count, 0, c.s));

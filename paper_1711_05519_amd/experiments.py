@@ -32,6 +32,7 @@ one warm-up). Each result is printed as one JSON line.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import time
@@ -133,6 +134,8 @@ def errtime(args):
 
 
 def many(args):
+    # the timed regions run with Python's collector held off (a collection of
+    # the host-side objects would otherwise land inside one of them)
     xs = [I.config_instance(5, i, keep_L=False) for i in range(args.count)]
     Ds = [torch.as_tensor(x.D, dtype=torch.float32, device="cuda") for x in xs]
 
@@ -143,20 +146,26 @@ def many(args):
     for sv in svs:          # warm-up
         sv.solve()
     torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
     its = [sv.solve().iterations for sv in svs]
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
+    gc.enable()
     emit(experiment="many", mode="one by one", count=args.count, seconds=t_seq, per_solve=t_seq / args.count,
          iterations=sum(its))
     for ns in (4, 8, 16):
         svs = solvers()
         R.solve_many(svs, n_streams=ns)     # warm-up
         torch.cuda.synchronize()
+        gc.collect()
+        gc.disable()
         t0 = time.perf_counter()
         infos = R.solve_many(svs, n_streams=ns)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
+        gc.enable()
         emit(experiment="many", mode=f"{ns} streams", count=args.count, seconds=t, per_solve=t / args.count,
              iterations=sum(i.iterations for i in infos), speedup=t_seq / t,
              same_iterations=[i.iterations for i in infos] == its)
@@ -174,10 +183,13 @@ def many(args):
     for _, bs in batches:   # warm-up
         bs.solve()
     torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
     res = [(idx, bs.solve()) for idx, bs in batches]
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    gc.enable()
     its_b = [0] * args.count
     for idx, infos in res:
         for i, info in zip(idx, infos):
