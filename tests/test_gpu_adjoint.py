@@ -139,3 +139,23 @@ def test_adjoint_rejects_bad_arguments():
     plain = R.Solver(dev(D), 2, p.beta, p.beta_init, p.gamma, p.mu)
     with pytest.raises(R.RpcaError):
         plain.unrolled_adjoint(ck, [1.0], [0.1], [1.0], Pd, Qd)  # no training workspace
+
+
+def test_unrolled_adjoint_at_the_limits():
+    """r = 10 (the largest rank of the relaxed iteration), a target of rank 16
+    and K = 15 unrolled bodies, FP64, against the oracle."""
+    m, n, r, K = 260, 240, 10, 15
+    rng = np.random.default_rng(5)
+    D, P0, Q0, U0, s0, V0, p = instance(m, n, r, 0.05, 9, 2.0, torch.float64)
+    # a target of rank 16: the true factors plus six small extra directions
+    P = np.hstack([P0, 1e-2 * rng.standard_normal((m, 6))])
+    Q = np.hstack([Q0, 1e-2 * rng.standard_normal((n, 6))])
+    T = P0 @ Q0.T
+    zetas = [0.9 * float(np.max(np.abs(T))) * 0.7 ** k for k in range(K)]
+    taus = [0.2 * z for z in zetas]
+    w = [1.0 / K] * K
+    losses, zb, Ub, sb, Vb = gpu_adjoint(D, P, Q, U0, s0, V0, p, zetas, taus, w, torch.float64)
+    ref = J.unrolled_adjoint(D, U0, s0, V0, zetas, taus, w, p, P, Q)
+    errs = (rel(losses, ref.losses), rel(zb, ref.zeta_bar), rel(Ub, ref.Ubar0), rel(sb, ref.sbar0), rel(Vb, ref.Vbar0))
+    say("  r=10 rt=16 K=15: losses %.2e  dzeta %.2e  dU0 %.2e  dsigma0 %.2e  dV0 %.2e" % errs)
+    assert max(errs) < 1e-7, errs

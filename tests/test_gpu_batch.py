@@ -155,3 +155,20 @@ def test_batch_training_pool_scale():
             x.D = None
     say(f"64 instances: {t_all * 1e3:.1f} ms in batches by rank, worst recovery error {worst:.2e}")
     assert worst <= 1e-4
+
+
+@pytest.mark.parametrize("m,n,dtype", [(300, 257, torch.float32), (129, 333, torch.float64)])
+def test_batch_unaligned_rows_and_single_instance(m, n, dtype):
+    """Rows whose length is not a whole number of 16-byte vectors take the
+    scalar path of the pass; a batch of one instance is the single solve."""
+    xs, p = draw(m, n, 2, 0.1, [71, 72, 73], 1e-5 if dtype == torch.float32 else 1e-7)
+    for group in (xs, xs[:1]):
+        bs = batch_of(group, p, dtype)
+        infos = bs.solve()
+        for i, (x, info) in enumerate(zip(group, infos)):
+            sv, ref = single(x, p, dtype)
+            d = rel(L_of(bs.U[i], bs.sigma[i], bs.V[i]), L_of(sv.U, sv.sigma, sv.V))
+            say(f"{m}x{n} {dtype} batch of {len(group)}, instance {i}: {info.iterations}/{ref.iterations}, rel L {d:.1e}")
+            assert info.status == ref.status == R.RPCA_OK
+            assert info.iterations == ref.iterations
+            assert d <= (1e-5 if dtype == torch.float32 else 1e-12)
