@@ -383,12 +383,10 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a_) {
     constexpr int RPB = GATHER_THREADS / GATHER_SPLIT;   // rows per workgroup
     constexpr bool GRAM = sizeof(T) == 4;
     Ctrl* ctrl = a.ctrl;
-    if (!body_runs(ctrl, a.body)) {
-        // A body queued past the end of its loop: the complement and update
-        // kernels that follow read `active` and must do nothing either.
-        if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->active = 0;
-        return;
-    }
+    // The gate is read here and tested once the tile sums are in LDS, so that
+    // its latency overlaps the loads of the partials (which are harmless in a
+    // body that does not run: they read the previous pass's partials).
+    const bool runs = body_runs(ctrl, a.body);
     __shared__ int flag;
     const int gU = (a.m + RPB - 1) / RPB;
     const bool uside = (int)blockIdx.x < gU;
@@ -473,6 +471,13 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a_) {
         }
     }
     if (a.lcorr && (int)threadIdx.x < K * K) gk[threadIdx.x] = gkv;
+    if (!runs) {
+        // A body queued past the end of its loop: the complement and update
+        // kernels that follow read `active` and must do nothing either.
+        // (The same decision in every workgroup: no barrier is left waiting.)
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->active = 0;
+        return;
+    }
     __syncthreads();
     double y[K];
 #pragma unroll
@@ -681,7 +686,9 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a_) {
         rec->id = a.body_id;
         __threadfence_system();
     }
-    if (from_m && !ctrl->active) return;
+    // `active` is tested after the loads of this workgroup's rows are issued
+    // (see below), so that the two latencies overlap.
+    const bool skip = from_m && !ctrl->active;
     __shared__ double sa[PANEL_THREADS * K], sb[PANEL_THREADS * K], sc[PANEL_THREADS * K];
     __shared__ double e1[K * K], e2[K * K], sig[K];
     __shared__ int flag;
@@ -722,6 +729,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a_) {
     }
     if (tid < K * K) { e1[tid] = e1v; e2[tid] = e2v; }
     if (tid < K) sig[tid] = sgv;
+    if (skip) return;   // the same in every workgroup
     __syncthreads();
     double gv[K], lf[K];   // the new basis row and the stored rebuild-factor row (zero past the end)
 #pragma unroll
