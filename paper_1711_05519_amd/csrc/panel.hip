@@ -145,7 +145,10 @@ constexpr double MLP_O_CLIP = 5.0;   // the correction exp(o) stays within e^-5 
 
 // Output o of the threshold network (parameters th, FP32, layout of the
 // training kernels) at features phi, evaluated in FP64 by one wave: lane j < 32
-// owns hidden unit j. The result is valid in every lane.
+// owns hidden unit j. The result is valid in every lane. W2T: the second
+// layer's weights are stored transposed (a copy in LDS, where lane j reading
+// row j of the row-major matrix would put all 32 lanes on one bank).
+template <bool W2T>
 __device__ __forceinline__ double w_mlp(const float* __restrict__ th, const double (&phi)[MLP_IN]) {
     constexpr int OB1 = MLP_H * MLP_IN, OW2 = OB1 + MLP_H, OB2 = OW2 + MLP_H * MLP_H, OW3 = OB2 + MLP_H,
                   OB3 = OW3 + MLP_H;
@@ -160,7 +163,8 @@ __device__ __forceinline__ double w_mlp(const float* __restrict__ th, const doub
     double c = 0.0;
     if (lane < MLP_H) {
         double v = th[OB2 + lane];
-        for (int i = 0; i < MLP_H; ++i) v = fma((double)th[OW2 + lane * MLP_H + i], h1s[i], v);
+        for (int i = 0; i < MLP_H; ++i)
+            v = fma((double)th[W2T ? OW2 + i * MLP_H + lane : OW2 + lane * MLP_H + i], h1s[i], v);
         c = (double)th[OW3 + lane] * fmax(v, 0.0);
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, WAVE);
@@ -179,7 +183,7 @@ __device__ __forceinline__ double w_mlp(const float* __restrict__ th, const doub
 template <int K>
 __device__ __forceinline__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const double* cs, const double* c2,
                            const double* g1, const double* g2, const double* ru, const double* rv,
-                           bool gram_form) {
+                           bool gram_form, const float* th, bool th_lds) {
     constexpr int N = 2 * K;
     __shared__ double r1[K * K], r1i[K * K], r2[K * K], r2i[K * K];
     __shared__ double Ma[N * N], Mv[N * N], Um[N * N], Vm[N * N], sg[N];
@@ -246,7 +250,7 @@ __device__ __forceinline__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const
     if (lane < N) sm->sigma_M[lane] = sg[lane];
     if (lane < K) sm->sigma_new[lane] = sg[lane];
     // threshold network on the features of this iterate (whole wave)
-    const bool use_mlp = ctrl->stage == STAGE_MAIN && ctrl->learned_on && a.mlp != nullptr;
+    const bool use_mlp = ctrl->stage == STAGE_MAIN && ctrl->learned_on && th != nullptr;
     double mlp_o = 0.0;
     if (use_mlp) {
         const int r = ctrl->r;
@@ -256,7 +260,7 @@ __device__ __forceinline__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const
         phi[1] = log(fmax(sg[r] / fmax(sg[0], f), MLP_SIGMA_RATIO_FLOOR));
         phi[2] = log(fmax(ctrl->err, f));
         phi[3] = log(fmax(sg[0], f) / fmax(sqrt(ctrl->normD2), f));
-        mlp_o = w_mlp(a.mlp, phi);
+        mlp_o = th_lds ? w_mlp<true>(th, phi) : w_mlp<false>(th, phi);
     }
     if (lane == 0) {
         const int r = ctrl->r;
@@ -544,7 +548,27 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a_) {
     __shared__ Ctrl cl;
     uint32_t cword = 0;
     if (threadIdx.x < CW) cword = reinterpret_cast<const uint32_t*>(ctrl)[threadIdx.x];
+    // The threshold network's parameters go to LDS for the tail (second
+    // layer transposed, see w_mlp): loaded with this phase's other loads,
+    // stored before the barrier of block_resid.
+    __shared__ float th_s[GRAM ? MLP_PARAMS : 1];
+    constexpr int TPT = GRAM ? (MLP_PARAMS + GATHER_THREADS - 1) / GATHER_THREADS : 1;
+    float thv[TPT];
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+        const int e = threadIdx.x + u * GATHER_THREADS;
+        thv[u] = (GRAM && a.mlp && e < MLP_PARAMS) ? a.mlp[e] : 0.f;
+    }
     block_sum_partials<K * K, GRAM ? 4 : 2, GATHER_THREADS>(a.gpart, gU, gV, sums, part);
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+        const int e = threadIdx.x + u * GATHER_THREADS;
+        if (GRAM && a.mlp && e < MLP_PARAMS) {
+            constexpr int OW2 = MLP_H * MLP_IN + MLP_H;
+            const int w = e - OW2;
+            th_s[(w >= 0 && w < MLP_H * MLP_H) ? OW2 + (w % MLP_H) * MLP_H + w / MLP_H : e] = thv[u];
+        }
+    }
     block_resid<GATHER_THREADS>(a.resid, a.n_tiles, sigma_stage, rv_, rw_, part, rsum);
     if (threadIdx.x >= WAVE) return;
     const int lane = lane_id();
@@ -604,7 +628,7 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a_) {
         w_mm2<K, true>(cs, cs, craw, c2, c2, craw2);
         for (int e = lane; e < K * K; e += WAVE) { g1[e] -= craw[e]; g2[e] -= craw2[e]; }
         wave_sync();
-        w_svd_tail<K>(a, ctrl, cs, c2, g1, g2, ru, rv, true);
+        w_svd_tail<K>(a, ctrl, cs, c2, g1, g2, ru, rv, true, a.mlp ? th_s : nullptr, true);
     }
     wave_sync();
     if (lane < CW) reinterpret_cast<uint32_t*>(cg)[lane] = reinterpret_cast<const uint32_t*>(&cl)[lane];
@@ -659,7 +683,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_complement(PanelArgs a_) {
     block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, a.gU, a.gV, gg, part);
     if (threadIdx.x >= WAVE) return;
     if (lane_id() == 0) ctrl->cnt[CNT_COMPLEMENT] = 0;
-    w_svd_tail<K>(a, ctrl, cs, c2, g1, g2, ru, rv, false);
+    w_svd_tail<K>(a, ctrl, cs, c2, g1, g2, ru, rv, false, a.mlp, false);
 }
 
 // ---- kernel 3: new factors (or entry from a given state), Trim, new bases ----

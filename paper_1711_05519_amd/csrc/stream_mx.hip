@@ -68,7 +68,7 @@ __device__ inline void mx_load_batch(const float* __restrict__ D, int64_t ldd, i
         const float* p = D + (size_t)i * ldd + jb;
         if constexpr (FULL) {
             if (i < i_hi) {
-                const float4 v = *reinterpret_cast<const float4*>(p);
+                const float4 v = load_once(reinterpret_cast<const float4*>(p));
                 d[b][0] = v.x; d[b][1] = v.y; d[b][2] = v.z; d[b][3] = v.w;
             } else {
 #pragma unroll
@@ -76,7 +76,7 @@ __device__ inline void mx_load_batch(const float* __restrict__ D, int64_t ldd, i
             }
         } else {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) d[b][s] = (i < i_hi && s < nvalid) ? p[s] : 0.f;
+            for (int s = 0; s < 4; ++s) d[b][s] = (i < i_hi && s < nvalid) ? load_once(p + s) : 0.f;
         }
     }
 }
