@@ -502,6 +502,10 @@ StreamArgs stream_args(const Ctx& c, const void* D, int body, const Geo& g) {
     a.body = body;
     a.batch = c.batch;
     a.slab = c.slab;
+    a.post_gpart = c.at<double>(c.L.off_gpart);
+    a.post_small = c.small();
+    a.post_gU = c.L.gU;
+    a.post_gV = c.L.gV;
     return a;
 }
 

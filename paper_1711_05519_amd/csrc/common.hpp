@@ -88,6 +88,8 @@ struct Ctrl {
     int32_t stopped_by_tol;
     int32_t active;      // 1 while the current loop body is live (set by the gather kernel)
     int32_t jacobi_sweeps;   // sweeps of the last 2K x 2K SVD (diagnostic)
+    int32_t post_update; // 1 (Gram only) or 2 (Gram and cross products): the update kernel left
+                         // the sums of its partials to workgroup 0 of the next streaming pass
     double zeta;         // threshold used by the next stream pass
     double err;          // err of the current state
     double normD2;       // ||D||_F^2

@@ -17,7 +17,7 @@ struct StreamArgs {
     const void* BL;       // n x K (T)
     const void* Uf;       // m x K (T): basis for Y2 = Z^T Uf
     const void* Vf;       // n x K (T): basis for Y1 = Z Vf
-    const Ctrl* ctrl;     // zeta, done
+    Ctrl* ctrl;           // zeta, done (read); post_update, cnt (completing an update)
     void* P1;             // [n_ct][m][K] partials of Y1 (acc type)
     void* P2;             // [n_rt][n][K] partials of Y2
     double* resid;        // [n_ct * n_rt] partial residual sums
@@ -27,6 +27,10 @@ struct StreamArgs {
     int32_t body;         // Body: gating of the launch
     int32_t batch;        // instances in the launch (grid y); every pointer above is
     int64_t slab;         // instance 0's, instance i's lies i * slab bytes further
+    // The update kernel's closing sums, left to this pass (ctrl->post_update):
+    double* post_gpart;   // its per-workgroup partials (gU + gV slots)
+    Small* post_small;    // destination of R_U^{-1}, R_V^{-1}, A_L^T U_f, B_L^T V_f
+    int32_t post_gU, post_gV;
 };
 
 // Scalar geometry of the streaming pass (kernel argument; pointers are passed
@@ -35,6 +39,9 @@ struct StreamGeom {
     int64_t ldd;
     int32_t m, n, TM, n_ct, n_rt, vec_ok, body;
     int64_t slab;         // bytes between the instances of a batched launch (0: one instance)
+    double* post_gpart;   // see StreamArgs (null: the pass never completes an update)
+    Small* post_small;
+    int32_t post_gU, post_gV;
 };
 
 struct MaterializeArgs {

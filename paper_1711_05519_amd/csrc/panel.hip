@@ -617,6 +617,7 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a_) {
         }
         ctrl->active = ctrl->done ? 0 : 1;
         ctrl->cnt[CNT_GATHER] = 0;
+        ctrl->post_update = 0;   // gpart now holds the gather's partials
         go_on = (GRAM && a.mode == GATHER_WITH_SVD && ctrl->active) ? 1 : 0;
     }
     go_on = __shfl(go_on, 0, WAVE);
@@ -817,25 +818,23 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a_) {
         rows_outer_sum2<K, PANEL_THREADS, PANEL_THREADS>(gv, lf, gv, true, threadIdx.x, sa, sc, sb, gp, gp + KMAX * KMAX);
     else
         rows_outer_sum<K, PANEL_THREADS, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, gp);
-    if (!last_block_arrives(&ctrl->cnt[CNT_UPDATE], &flag)) return;
-    __shared__ double gg[4 * K * K], rr[K * K], ri[K * K], rr2[K * K], ri2[K * K], part[PANEL_THREADS];
-    double* g = gg;
-    double* gb = gg + K * K;
-    if (main_stage) block_sum_partials<K * K, 4, PANEL_THREADS, 32>(a.gpart, a.gU, a.gV, gg, part);
-    else block_sum_partials<K * K, 2, PANEL_THREADS>(a.gpart, a.gU, a.gV, gg, part);
-    if (threadIdx.x >= WAVE) return;
-    const bool exact = a.mode == UPDATE_ENTER_EXACT;
-    if (main_stage) {
-        w_store<K>(gg + 2 * K * K, a.small->GAU);
-        w_store<K>(gg + 3 * K * K, a.small->GBV);
+    if (from_m) {
+        // Inside a loop the next kernel is a streaming pass; its workgroup 0
+        // sums these partials (finish_basis) once its tile is done, off the
+        // critical path: the results are first read by the gather after it.
+        if (blockIdx.x == 0) {
+            if (a.sigma_dst && threadIdx.x < K) a.sigma_dst[threadIdx.x] = sig[threadIdx.x];
+            if (threadIdx.x == 0) ctrl->post_update = main_stage ? 2 : 1;
+        }
+        return;
     }
-    w_chol_inv2<K>(g, rr, ri, gb, rr2, ri2);
-    w_store<K>(ri, exact ? a.small->RAinv : a.small->RUinv);
-    w_store<K>(ri2, exact ? a.small->RBinv : a.small->RVinv);
+    if (!last_block_arrives(&ctrl->cnt[CNT_UPDATE], &flag)) return;
+    finish_basis<K, PANEL_THREADS, 32>(a.gpart, a.gU, a.gV, main_stage, a.mode == UPDATE_ENTER_EXACT, a.small);
     const int lane = lane_id();
-    if (a.sigma_dst && lane < K) a.sigma_dst[lane] = sig[lane];
-    if (lane == 0) {
-        if (!from_m && ctrl->stage == STAGE_INIT_DONE) ctrl->stage = STAGE_MAIN;
+    if (threadIdx.x < WAVE && a.sigma_dst && lane < K) a.sigma_dst[lane] = sig[lane];
+    if (threadIdx.x == 0) {
+        if (ctrl->stage == STAGE_INIT_DONE) ctrl->stage = STAGE_MAIN;
+        ctrl->post_update = 0;   // nothing left for the next pass
         ctrl->cnt[CNT_UPDATE] = 0;
     }
 }
@@ -872,7 +871,10 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_cross(PanelArgs a_) {
     if (threadIdx.x >= WAVE) return;
     w_store<K>(gg, a.small->GAU);
     w_store<K>(gg + K * K, a.small->GBV);
-    if (lane_id() == 0) ctrl->cnt[CNT_CROSS] = 0;
+    if (lane_id() == 0) {
+        ctrl->cnt[CNT_CROSS] = 0;
+        ctrl->post_update = 0;   // gpart now holds these partials, not an update's
+    }
 }
 
 // ---- FP64 orthonormal bases U~ = A R_A^{-1} of the trimmed factors ------------
@@ -942,7 +944,10 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_start(PanelArgs a_) {
     w_chol_inv2<K>(g, rr, ri, gb, rr2, ri2);
     w_store<K>(ri, a.small->RUinv);
     w_store<K>(ri2, a.small->RVinv);
-    if (lane_id() == 0) ctrl->cnt[CNT_START] = 0;
+    if (lane_id() == 0) {
+        ctrl->cnt[CNT_START] = 0;
+        ctrl->post_update = 0;
+    }
 }
 
 __global__ void k_setup(Ctrl* ctrl, Ctrl init, int64_t slab) {

@@ -22,6 +22,7 @@
 // sum per lane. Tile partials go to P1/P2 and are summed in FP64 by the gather
 // kernel in a fixed order, so results are bitwise reproducible.
 #include "launch.hpp"
+#include "wave.hpp"
 
 namespace rpca {
 namespace {
@@ -281,7 +282,7 @@ template <typename T, int K, bool REBUILD>
 __global__ __launch_bounds__(STREAM_THREADS) void k_stream(
     const T* __restrict__ D, const T* __restrict__ AL, const T* __restrict__ BL, const T* __restrict__ Uf,
     const T* __restrict__ Vf, typename AccOf<T>::type* __restrict__ P1, typename AccOf<T>::type* __restrict__ P2,
-    double* __restrict__ resid, const Ctrl* __restrict__ ctrl, StreamGeom g) {
+    double* __restrict__ resid, Ctrl* __restrict__ ctrl, StreamGeom g) {
     using Acc = typename AccOf<T>::type;
     {   // instance blockIdx.y of a batched launch (slab 0: a single instance)
         const int64_t off = (int64_t)blockIdx.y * g.slab;
@@ -364,6 +365,7 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream(
             resid[gridDim.x + tile] = mx;
         }
     }
+    pass_finishes_update<K, STREAM_THREADS>(ctrl, g, (int64_t)blockIdx.y * g.slab);
 }
 
 // Dense L = AL BL^T and S = T_zeta(D - L) (outputs of Algorithm 1).
@@ -424,6 +426,10 @@ hipError_t stream_dispatch(const StreamArgs& a, int K, hipStream_t s) {
     geom.n_rt = a.n_rt;
     geom.vec_ok = a.vec_ok;
     geom.body = a.body;
+    geom.post_gpart = a.post_gpart;
+    geom.post_small = a.post_small;
+    geom.post_gU = a.post_gU;
+    geom.post_gV = a.post_gV;
     switch (K) {
 #define RPCA_CASE(KK)                                                                                      \
     case KK:                                                                                               \

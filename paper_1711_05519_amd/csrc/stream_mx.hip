@@ -30,6 +30,7 @@
 // gather is shared.
 
 #include "launch.hpp"
+#include "wave.hpp"
 
 namespace rpca {
 namespace {
@@ -215,7 +216,7 @@ template <int K, bool REBUILD>
 __global__ __launch_bounds__(STREAM_THREADS) void k_stream_mx(
     const float* __restrict__ D, const float* __restrict__ AL, const float* __restrict__ BL,
     const float* __restrict__ Uf, const float* __restrict__ Vf, float* __restrict__ P1, float* __restrict__ P2,
-    double* __restrict__ resid, const Ctrl* __restrict__ ctrl, StreamGeom g) {
+    double* __restrict__ resid, Ctrl* __restrict__ ctrl, StreamGeom g) {
     static_assert(K <= 16, "MFMA N = 16 holds up to 16 columns");
     {   // instance blockIdx.y of a batched launch (slab 0: a single instance)
         const int64_t off = (int64_t)blockIdx.y * g.slab;
@@ -306,6 +307,7 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream_mx(
             resid[gridDim.x + tile] = mx;
         }
     }
+    pass_finishes_update<K, STREAM_THREADS>(ctrl, g, (int64_t)blockIdx.y * g.slab);
 }
 
 template <bool REBUILD>
@@ -321,6 +323,10 @@ hipError_t mx_dispatch(const StreamArgs& a, int K, hipStream_t s) {
     geom.n_rt = a.n_rt;
     geom.vec_ok = a.vec_ok;
     geom.body = a.body;
+    geom.post_gpart = a.post_gpart;
+    geom.post_small = a.post_small;
+    geom.post_gU = a.post_gU;
+    geom.post_gV = a.post_gV;
     switch (K) {
 #define RPCA_CASE(KK)                                                                                        \
     case KK:                                                                                                 \

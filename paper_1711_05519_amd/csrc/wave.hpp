@@ -5,7 +5,7 @@
 // relaxed iteration.
 #pragma once
 
-#include "common.hpp"
+#include "launch.hpp"
 
 namespace rpca {
 namespace {
@@ -410,6 +410,54 @@ __device__ __forceinline__ int wave_jacobi_svd(double* A, double* V, double* sig
     }
     wave_sync();
     return sweep + 1;
+}
+
+// ---- the update kernel's closing sums -----------------------------------------
+//
+// Sums of the per-workgroup partials the update kernel leaves in gpart (gU U
+// side, gV V side) and what follows from them: Gram(U_f) = R_U^T R_U and
+// Gram(V_f) = R_V^T R_V (R^{-1} by Cholesky, into RUinv/RVinv, or RAinv/RBinv
+// for the exact bases) and, with cross, A_L^T U_f and B_L^T V_f (GAU, GBV)
+// for the gather of the next rebuilding pass. The whole workgroup (NT threads)
+// sums in a fixed order; its first wave factorises. Run by the update kernel's
+// last workgroup when it enters from a given state, and otherwise by the first
+// workgroup to finish the streaming pass that follows (ctrl->post_update).
+// L: loads in flight per thread (the order of the sums, and so the result,
+// does not depend on it).
+template <int K, int NT, int L>
+__device__ __forceinline__ void finish_basis(const double* __restrict__ gpart, int gU, int gV, bool cross,
+                                             bool exact, Small* sm) {
+    __shared__ double gg[4 * K * K], rr[K * K], ri[K * K], rr2[K * K], ri2[K * K], part[NT];
+    if (cross) block_sum_partials<K * K, 4, NT, L>(gpart, gU, gV, gg, part);
+    else block_sum_partials<K * K, 2, NT, L>(gpart, gU, gV, gg, part);
+    if (threadIdx.x < WAVE) {
+        if (cross) {
+            w_store<K>(gg + 2 * K * K, sm->GAU);
+            w_store<K>(gg + 3 * K * K, sm->GBV);
+        }
+        w_chol_inv2<K>(gg, rr, ri, gg + K * K, rr2, ri2);
+        w_store<K>(ri, exact ? sm->RAinv : sm->RUinv);
+        w_store<K>(ri2, exact ? sm->RBinv : sm->RVinv);
+    }
+}
+
+// End of a streaming-pass workgroup: workgroup 0 of the launch (of each
+// instance), which starts first on its CU and is among the first to finish,
+// completes the update kernel that preceded the pass when that kernel left
+// its closing sums to the pass (post_update 1: Grams, 2: Grams and cross
+// products). Its results are first read by the gather after the pass. The
+// flag is set by the update kernel and cleared here and by every other kernel
+// that overwrites the partials.
+template <int K, int NT>
+__device__ __forceinline__ void pass_finishes_update(Ctrl* ctrl, const StreamGeom& g, int64_t off) {
+    if (g.post_gpart == nullptr || blockIdx.x != 0) return;
+    const int mode = ctrl->post_update;
+    if (mode == 0) return;
+    // few loads in flight: the pass's own registers bound the kernel, and this
+    // work is off the critical path
+    finish_basis<K, NT, 4>(moved(g.post_gpart, off), g.post_gU, g.post_gV, mode == 2, false,
+                           moved(g.post_small, off));
+    if (threadIdx.x == 0) ctrl->post_update = 0;
 }
 
 }  // namespace
