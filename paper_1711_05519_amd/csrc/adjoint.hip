@@ -244,7 +244,7 @@ __global__ __launch_bounds__(RX_THREADS) void k_adj_stream(AdjStream a) {
     __shared__ double bred[RX_THREADS / WAVE];
     double res = 0.0, zsum = 0.0;
     for (int i = i_lo; i < i_hi; ++i) {
-        double x = valid ? static_cast<double>(load_once(D + (size_t)i * a.ldd + j)) : 0.0;
+        double x = valid ? static_cast<double>(D[(size_t)i * a.ldd + j]) : 0.0;
         const double d = x;
 #pragma unroll
         for (int t = 0; t < K; ++t) x = fma(-(a.U[(size_t)i * K + t] * a.sig[t]), vb[t], x);

@@ -182,22 +182,34 @@ __device__ inline int xcd_tile(int b, int G) {
     return (x < rm ? x * (q + 1) : rm * (q + 1) + (x - rm) * q) + pos;
 }
 
-// Loads of D, which every pass reads exactly once: marked non-temporal, so that
-// streaming the m x n data does not evict from the L2 what the kernels around
-// the pass reuse (bases, partial sums, code). Measured at m = n = 10^4, r = 5:
-// FP32 loop pass 97.2 -> 95.6 us, whole loop body 147.9 -> 144.2 us.
+// Loads of D, which every pass reads exactly once. NT: marked non-temporal, so
+// that streaming the m x n data does not evict from the L2 what the kernels
+// around the pass reuse (bases, partial sums, code). Measured at
+// m = n = 10^4, r = 5: FP32 loop pass 97.2 -> 95.6 us, initialisation pass
+// 98.2 -> 94.8 us, loop body 147.9 -> 144.2 us; at m = n = 2 10^4, r = 10,
+// where the pass is bound by its vector ALU work, the loop pass went from
+// 641 to 675 us. Passes use them for blocks of up to D_LOADS_NT_KMAX columns.
+constexpr int D_LOADS_NT_KMAX = 6;
 typedef float nt_float4 __attribute__((ext_vector_type(4)));
 typedef double nt_double2 __attribute__((ext_vector_type(2)));
-__device__ inline float4 load_once(const float4* p) {
+template <bool NT> __device__ inline float4 load_d(const float4* p) {
+    if constexpr (!NT) return *p;
     const nt_float4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_float4*>(p));
     return make_float4(v.x, v.y, v.z, v.w);
 }
-__device__ inline double2 load_once(const double2* p) {
+template <bool NT> __device__ inline double2 load_d(const double2* p) {
+    if constexpr (!NT) return *p;
     const nt_double2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_double2*>(p));
     return make_double2(v.x, v.y);
 }
-__device__ inline float load_once(const float* p) { return __builtin_nontemporal_load(p); }
-__device__ inline double load_once(const double* p) { return __builtin_nontemporal_load(p); }
+template <bool NT> __device__ inline float load_d(const float* p) {
+    if constexpr (!NT) return *p;
+    return __builtin_nontemporal_load(p);
+}
+template <bool NT> __device__ inline double load_d(const double* p) {
+    if constexpr (!NT) return *p;
+    return __builtin_nontemporal_load(p);
+}
 
 // p moved by off bytes (the data of another instance of a batched launch);
 // a null pointer stays null.

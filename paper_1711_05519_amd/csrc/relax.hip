@@ -68,7 +68,7 @@ __global__ __launch_bounds__(RX_THREADS) void k_relax_stream(RelaxArgs a) {
     double res = 0.0;
     for (int i = i_lo; i < i_hi; ++i) {
         double p[K2];
-        double x = valid ? static_cast<double>(load_once(D + (size_t)i * a.ldd + j)) : 0.0;
+        double x = valid ? static_cast<double>(D[(size_t)i * a.ldd + j]) : 0.0;
         const double d = x;
 #pragma unroll
         for (int t = 0; t < K; ++t) x -= static_cast<double>(AL[(size_t)i * K + t]) * bl[t];

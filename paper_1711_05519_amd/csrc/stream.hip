@@ -141,23 +141,25 @@ __device__ inline int bitrev6(int l) {
 
 // ---- loads of 4 consecutive elements -----------------------------------------
 
+template <bool NT>
 __device__ inline void load4(const float* __restrict__ p, int nvalid, bool vec, float (&d)[4]) {
     if (nvalid == 4 && vec) {
-        const float4 v = load_once(reinterpret_cast<const float4*>(p));
+        const float4 v = load_d<NT>(reinterpret_cast<const float4*>(p));
         d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
     } else {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) d[s] = s < nvalid ? load_once(p + s) : 0.f;
+        for (int s = 0; s < 4; ++s) d[s] = s < nvalid ? load_d<NT>(p + s) : 0.f;
     }
 }
+template <bool NT>
 __device__ inline void load4(const double* __restrict__ p, int nvalid, bool vec, double (&d)[4]) {
     if (nvalid == 4 && vec) {
-        const double2 v0 = load_once(reinterpret_cast<const double2*>(p));
-        const double2 v1 = load_once(reinterpret_cast<const double2*>(p) + 1);
+        const double2 v0 = load_d<NT>(reinterpret_cast<const double2*>(p));
+        const double2 v1 = load_d<NT>(reinterpret_cast<const double2*>(p) + 1);
         d[0] = v0.x; d[1] = v0.y; d[2] = v1.x; d[3] = v1.y;
     } else {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) d[s] = s < nvalid ? load_once(p + s) : 0.0;
+        for (int s = 0; s < 4; ++s) d[s] = s < nvalid ? load_d<NT>(p + s) : 0.0;
     }
 }
 
@@ -182,7 +184,7 @@ __device__ __forceinline__ void load_batch(const T* __restrict__ D, int64_t ldd,
     for (int b = 0; b < NB; ++b) {
         const int i = i0 + STREAM_WAVES * b;
         if (!CHECK || i < i_hi) {
-            load4(D + (size_t)i * ldd + jb, FULL ? STREAM_CPL : nvalid, FULL, d[b]);
+            load4<(K <= D_LOADS_NT_KMAX)>(D + (size_t)i * ldd + jb, FULL ? STREAM_CPL : nvalid, FULL, d[b]);
         } else {
 #pragma unroll
             for (int s = 0; s < STREAM_CPL; ++s) d[b][s] = T(0);

@@ -60,7 +60,7 @@ __device__ inline uint16_t bf16_bits(float x) { return __builtin_bit_cast(uint16
 // NBT rows x 4 columns of D for one lane (zeros outside the matrix).
 // FULL: the tile's 256 columns are inside D and rows are 16-byte aligned, so
 // only the (wave-uniform) row bound is checked.
-template <int NBT, bool FULL>
+template <int NBT, bool FULL, bool NT>
 __device__ inline void mx_load_batch(const float* __restrict__ D, int64_t ldd, int i0, int i_hi, int jb, int nvalid,
                                      float (&d)[NBT][4]) {
 #pragma unroll
@@ -69,7 +69,7 @@ __device__ inline void mx_load_batch(const float* __restrict__ D, int64_t ldd, i
         const float* p = D + (size_t)i * ldd + jb;
         if constexpr (FULL) {
             if (i < i_hi) {
-                const float4 v = load_once(reinterpret_cast<const float4*>(p));
+                const float4 v = load_d<NT>(reinterpret_cast<const float4*>(p));
                 d[b][0] = v.x; d[b][1] = v.y; d[b][2] = v.z; d[b][3] = v.w;
             } else {
 #pragma unroll
@@ -77,7 +77,7 @@ __device__ inline void mx_load_batch(const float* __restrict__ D, int64_t ldd, i
             }
         } else {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) d[b][s] = (i < i_hi && s < nvalid) ? load_once(p + s) : 0.f;
+            for (int s = 0; s < 4; ++s) d[b][s] = (i < i_hi && s < nvalid) ? load_d<NT>(p + s) : 0.f;
         }
     }
 }
@@ -137,7 +137,7 @@ __device__ inline void mx_tile(const float* __restrict__ D, const float* __restr
     const int nblk = i_hi > i_lo ? (i_hi - i_lo + MX_RB - 1) / MX_RB : 0;
     const int rounds = (nblk + STREAM_WAVES - 1) / STREAM_WAVES;
     int i0 = i_lo + MX_RB * wave;
-    if (rounds > 0) mx_load_batch<NBT, FULL>(D, g.ldd, i0, i_hi, jb, nvalid, ba);
+    if (rounds > 0) mx_load_batch<NBT, FULL, (K <= D_LOADS_NT_KMAX)>(D, g.ldd, i0, i_hi, jb, nvalid, ba);
     for (int rd = 0; rd < rounds; ++rd, i0 += MX_RB * STREAM_WAVES) {
         float rs = 0.f;
         // phase A: batches of NBT rows in two register buffers; the loads
@@ -146,7 +146,7 @@ __device__ inline void mx_tile(const float* __restrict__ D, const float* __restr
         const int i_next = i0 + MX_RB * STREAM_WAVES;
 #pragma unroll 1
         for (int bt = 0; bt < MX_RB / NBT; bt += 2) {
-            mx_load_batch<NBT, FULL>(D, g.ldd, i0 + NBT * (bt + 1), i_hi, jb, nvalid, bb);
+            mx_load_batch<NBT, FULL, (K <= D_LOADS_NT_KMAX)>(D, g.ldd, i0 + NBT * (bt + 1), i_hi, jb, nvalid, bb);
             if (i0 + NBT * (bt + 1) <= i_hi)
                 mx_compute_batch<K, NBT, REBUILD, false>(ba, AL, i0 + NBT * bt, i_hi, NBT * bt, zeta, bl, zl, lane,
                                                          rs, amax);
@@ -154,7 +154,7 @@ __device__ inline void mx_tile(const float* __restrict__ D, const float* __restr
                 mx_compute_batch<K, NBT, REBUILD, true>(ba, AL, i0 + NBT * bt, i_hi, NBT * bt, zeta, bl, zl, lane,
                                                         rs, amax);
             const int inx = (bt + 2 < MX_RB / NBT) ? i0 + NBT * (bt + 2) : i_next;
-            mx_load_batch<NBT, FULL>(D, g.ldd, inx, i_hi, jb, nvalid, ba);
+            mx_load_batch<NBT, FULL, (K <= D_LOADS_NT_KMAX)>(D, g.ldd, inx, i_hi, jb, nvalid, ba);
             if (i0 + NBT * (bt + 2) <= i_hi)
                 mx_compute_batch<K, NBT, REBUILD, false>(bb, AL, i0 + NBT * (bt + 1), i_hi, NBT * (bt + 1), zeta,
                                                          bl, zl, lane, rs, amax);
