@@ -335,7 +335,11 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream(
                                           amax, P1t, lane);
 
     // E^T Uf partial: sum the four waves' column partials through LDS.
-    __shared__ Acc sm[STREAM_TN * K];
+    // the column partials; afterwards, scratch of pass_finishes_update
+    constexpr int SM_BYTES = STREAM_TN * K * (int)sizeof(Acc);
+    constexpr int FIN_BYTES = FINISH_LDS<K, STREAM_THREADS>() * (int)sizeof(double);
+    __shared__ __align__(16) unsigned char sm_raw[SM_BYTES > FIN_BYTES ? SM_BYTES : FIN_BYTES];
+    Acc* sm = reinterpret_cast<Acc*>(sm_raw);
     __shared__ double red[STREAM_WAVES];
     for (int w = 0; w < STREAM_WAVES; ++w) {
         if (wave == w) {
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream(
             resid[gridDim.x + tile] = mx;
         }
     }
-    pass_finishes_update<K, STREAM_THREADS>(ctrl, g, (int64_t)blockIdx.y * g.slab);
+    pass_finishes_update<K, STREAM_THREADS>(ctrl, g, (int64_t)blockIdx.y * g.slab, reinterpret_cast<double*>(sm_raw));
 }
 
 // Dense L = AL BL^T and S = T_zeta(D - L) (outputs of Algorithm 1).

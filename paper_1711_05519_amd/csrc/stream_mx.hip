@@ -245,7 +245,9 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream_mx(
     const int i_lo = rt * g.TM;
     const int i_hi = min(g.m, i_lo + g.TM);
 
-    __shared__ uint16_t zbuf[STREAM_WAVES][MX_RB * MX_PITCH];
+    // E blocks; afterwards, scratch of pass_finishes_update
+    __shared__ __align__(16) uint16_t zbuf[STREAM_WAVES][MX_RB * MX_PITCH];
+    static_assert(sizeof(zbuf) >= FINISH_LDS<K, STREAM_THREADS>() * sizeof(double), "scratch of the closing sums");
     __shared__ __align__(8) uint16_t ul[K * MX_UPITCH];
     __shared__ double red[STREAM_WAVES];
     // B operands of Y1 in LDS: for (32-column block kb, k group lg, column t
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream_mx(
             resid[gridDim.x + tile] = mx;
         }
     }
-    pass_finishes_update<K, STREAM_THREADS>(ctrl, g, (int64_t)blockIdx.y * g.slab);
+    pass_finishes_update<K, STREAM_THREADS>(ctrl, g, (int64_t)blockIdx.y * g.slab, reinterpret_cast<double*>(&zbuf[0][0]));
 }
 
 template <bool REBUILD>

@@ -423,11 +423,17 @@ __device__ __forceinline__ int wave_jacobi_svd(double* A, double* V, double* sig
 // last workgroup when it enters from a given state, and otherwise by the first
 // workgroup to finish the streaming pass that follows (ctrl->post_update).
 // L: loads in flight per thread (the order of the sums, and so the result,
-// does not depend on it).
+// does not depend on it). lds: FINISH_LDS<K, NT>() doubles of LDS scratch.
+template <int K, int NT> constexpr int FINISH_LDS() { return 8 * K * K + NT; }
 template <int K, int NT, int L>
 __device__ __forceinline__ void finish_basis(const double* __restrict__ gpart, int gU, int gV, bool cross,
-                                             bool exact, Small* sm) {
-    __shared__ double gg[4 * K * K], rr[K * K], ri[K * K], rr2[K * K], ri2[K * K], part[NT];
+                                             bool exact, Small* sm, double* lds) {
+    double* gg = lds;                 // 4 K^2: the four sums
+    double* rr = gg + 4 * K * K;      // K^2 each: R_U, R_U^{-1}, R_V, R_V^{-1}
+    double* ri = rr + K * K;
+    double* rr2 = ri + K * K;
+    double* ri2 = rr2 + K * K;
+    double* part = ri2 + K * K;       // NT
     if (cross) block_sum_partials<K * K, 4, NT, L>(gpart, gU, gV, gg, part);
     else block_sum_partials<K * K, 2, NT, L>(gpart, gU, gV, gg, part);
     if (threadIdx.x < WAVE) {
@@ -448,15 +454,20 @@ __device__ __forceinline__ void finish_basis(const double* __restrict__ gpart, i
 // products). Its results are first read by the gather after the pass. The
 // flag is set by the update kernel and cleared here and by every other kernel
 // that overwrites the partials.
+// lds: FINISH_LDS<K, NT>() doubles of the pass's LDS, free once its tile is
+// done (the barrier below separates the two uses).
 template <int K, int NT>
-__device__ __forceinline__ void pass_finishes_update(Ctrl* ctrl, const StreamGeom& g, int64_t off) {
+__device__ __forceinline__ void pass_finishes_update(Ctrl* ctrl, const StreamGeom& g, int64_t off, double* lds) {
     if (g.post_gpart == nullptr || blockIdx.x != 0) return;
     const int mode = ctrl->post_update;
     if (mode == 0) return;
-    // few loads in flight: the pass's own registers bound the kernel, and this
-    // work is off the critical path
-    finish_basis<K, NT, 4>(moved(g.post_gpart, off), g.post_gU, g.post_gV, mode == 2, false,
-                           moved(g.post_small, off));
+    __syncthreads();
+    // 32 loads in flight per thread, as in the update kernel: with fewer, a
+    // sum over the 2 x 79 partials of m = n = 2 10^4 takes tens of dependent
+    // round trips and can outlast the pass (the pass's own registers still
+    // bound the kernel's)
+    finish_basis<K, NT, 32>(moved(g.post_gpart, off), g.post_gU, g.post_gV, mode == 2, false,
+                           moved(g.post_small, off), lds);
     if (threadIdx.x == 0) ctrl->post_update = 0;
 }
 
