@@ -573,7 +573,6 @@ int enqueue_body(const Ctx& c, const void* D, int K, int body, double* state_U, 
     if (!fp32) HIP_TRY(launch_complement(pa, K, c.dtype, c.s));
     PanelArgs ua = pa;
     ua.mode = UPDATE_FROM_M;
-    ua.defer = K <= POST_DEFER_KMAX ? 1 : 0;
     ua.body_id = body_id;
     ua.S2U = fp32 ? pa.Y1 : pa.W1;
     ua.S2V = fp32 ? pa.Y2 : pa.W2;

@@ -92,13 +92,7 @@ struct PanelArgs {
     int64_t slab;             // bytes between instances: every pointer but mlp and host_status
                               // is instance 0's and is moved by blockIdx.y * slab
     int32_t lcorr;            // gather: the pass rebuilt L; add AL GBV to Y1 and BL GAU to Y2
-    int32_t defer;            // update (loop body): leave the closing sums to the next pass
 };
-
-// Widest block whose update leaves its closing sums to the next pass: beyond
-// it the sums (4 K^2 entries over the update's partials) take longer than the
-// pass's first workgroup has left (measured at r = 10: BF16 pass +25 us).
-constexpr int POST_DEFER_KMAX = 8;
 
 // Results of one relaxed iteration (device, written by its tail kernel).
 struct RelaxResult {

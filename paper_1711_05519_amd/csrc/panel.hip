@@ -818,7 +818,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a_) {
         rows_outer_sum2<K, PANEL_THREADS, PANEL_THREADS>(gv, lf, gv, true, threadIdx.x, sa, sc, sb, gp, gp + KMAX * KMAX);
     else
         rows_outer_sum<K, PANEL_THREADS, PANEL_THREADS>(gv, gv, true, threadIdx.x, sa, sb, gp);
-    if (from_m && a.defer) {
+    if (from_m) {
         // Inside a loop the next kernel is a streaming pass; its workgroup 0
         // sums these partials (finish_basis) once its tile is done, off the
         // critical path: the results are first read by the gather after it.
@@ -835,7 +835,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_update(PanelArgs a_) {
     const int lane = lane_id();
     if (threadIdx.x < WAVE && a.sigma_dst && lane < K) a.sigma_dst[lane] = sig[lane];
     if (threadIdx.x == 0) {
-        if (!from_m && ctrl->stage == STAGE_INIT_DONE) ctrl->stage = STAGE_MAIN;
+        if (ctrl->stage == STAGE_INIT_DONE) ctrl->stage = STAGE_MAIN;
         ctrl->post_update = 0;   // nothing left for the next pass
         ctrl->cnt[CNT_UPDATE] = 0;
     }
