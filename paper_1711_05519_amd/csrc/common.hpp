@@ -223,13 +223,15 @@ template <typename X> __device__ inline X* moved(X* p, int64_t off) {
     return reinterpret_cast<X*>(reinterpret_cast<C*>(p) + off);
 }
 
+// The increment releases (agent scope) the workgroup's results; only the
+// last workgroup acquires, so the others skip the L2 invalidation a full
+// fence costs.
 __device__ inline bool last_block_arrives(uint32_t* counter, int* flag_smem) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(counter, 1u);
+        const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         const int last = (prev == gridDim.x - 1) ? 1 : 0;
-        if (last) __threadfence();
+        if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *flag_smem = last;
     }
     __syncthreads();
