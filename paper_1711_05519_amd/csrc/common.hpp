@@ -188,7 +188,9 @@ __device__ inline int xcd_tile(int b, int G) {
 // m = n = 10^4, r = 5: FP32 loop pass 97.2 -> 95.6 us, initialisation pass
 // 98.2 -> 94.8 us, loop body 147.9 -> 144.2 us; at m = n = 2 10^4, r = 10,
 // where the pass is bound by its vector ALU work, the loop pass went from
-// 641 to 675 us. Passes use them for blocks of up to D_LOADS_NT_KMAX columns.
+// 641 to 675 us, and FP64 passes (8-byte D) were slower with them at every
+// size measured (m = n = 5000: solve 2.09 -> 2.43 ms). Passes over FP32 D use
+// them for blocks of up to D_LOADS_NT_KMAX columns.
 constexpr int D_LOADS_NT_KMAX = 6;
 typedef float nt_float4 __attribute__((ext_vector_type(4)));
 typedef double nt_double2 __attribute__((ext_vector_type(2)));

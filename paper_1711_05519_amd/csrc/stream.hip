@@ -184,7 +184,8 @@ __device__ __forceinline__ void load_batch(const T* __restrict__ D, int64_t ldd,
     for (int b = 0; b < NB; ++b) {
         const int i = i0 + STREAM_WAVES * b;
         if (!CHECK || i < i_hi) {
-            load4<(K <= D_LOADS_NT_KMAX)>(D + (size_t)i * ldd + jb, FULL ? STREAM_CPL : nvalid, FULL, d[b]);
+            load4<(K <= D_LOADS_NT_KMAX && sizeof(T) == 4)>(D + (size_t)i * ldd + jb, FULL ? STREAM_CPL : nvalid,
+                                                             FULL, d[b]);
         } else {
 #pragma unroll
             for (int s = 0; s < STREAM_CPL; ++s) d[b][s] = T(0);
