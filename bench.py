@@ -45,8 +45,8 @@ HBM_PEAK_GBPS = 8000.0
 # FETCH_SIZE / WRITE_SIZE counter runs scaled by a device copy of known size
 # (profiles/k_stream_f32_r5_traffic.md); valid while the kernel source is the
 # one measured.
-TRAFFIC_BYTES = {2: 428.2e6}   # by workload configuration
-TRAFFIC_SOURCE = ("paper_1711_05519_amd/csrc/stream.hip", "dda064df94426302")
+TRAFFIC_BYTES = {2: 428.4e6}   # by workload configuration
+TRAFFIC_SOURCE = ("paper_1711_05519_amd/csrc/stream.hip", "069f501782a9f300")
 
 
 def parse():
