@@ -933,14 +933,26 @@ public:
     // After the last body: waits for the stream, then fills the state and the
     // histories. Returns rpca_solve's status.
     int finish() {
+        // the last kernel copies the control block and the histories' leading
+        // entries into the status slot: one synchronisation reads them all
+        if (rc_ >= 0) {
+            const hipError_t le =
+                launch_publish(c_.ctrl(), c_.err_hist(), c_.zeta_hist(), p_->max_iter + 1, c_.st_dev, c_.s);
+            if (le != hipSuccess) {
+                g_last_hip_error = (int)le;
+                rc_ = RPCA_EHIP;
+            }
+        }
         hipError_t e = hipStreamSynchronize(c_.s);
         if (e != hipSuccess && rc_ >= 0) {
             g_last_hip_error = (int)e;
             rc_ = RPCA_EHIP;
         }
         RPCA_TRY(rc_);
+        const volatile HostStatus* hs = c_.st_host;
+        std::atomic_thread_fence(std::memory_order_acquire);
         Ctrl fin;
-        RPCA_TRY(read_ctrl(c_, &fin));
+        memcpy(&fin, const_cast<const Ctrl*>(&hs->fin), sizeof(Ctrl));
         if (fin.nonfinite == 1) return RPCA_EINVAL;       // ||D||_F = 0 or a non-finite entry of D
         if (fin.nonfinite) return RPCA_EBREAKDOWN;        // a non-finite residual inside the loop
         if (fin.stage != STAGE_MAIN) return RPCA_EHIP;   // unreachable: the pass cap forces convergence
@@ -948,11 +960,18 @@ public:
         st_->init_passes = fin.total_passes;
         const int n = fin.k + 1;
         const int cnt = n < hist_cap_ ? n : hist_cap_;
-        if (cnt > 0 && err_hist_)
-            HIP_TRY(hipMemcpyAsync(err_hist_, c_.err_hist(), sizeof(double) * cnt, hipMemcpyDeviceToHost, c_.s));
-        if (cnt > 0 && zeta_hist_)
-            HIP_TRY(hipMemcpyAsync(zeta_hist_, c_.zeta_hist(), sizeof(double) * cnt, hipMemcpyDeviceToHost, c_.s));
-        HIP_TRY(hipStreamSynchronize(c_.s));
+        if (cnt > 0 && cnt <= PUBLISH_HIST) {
+            for (int i = 0; i < cnt; ++i) {
+                if (err_hist_) err_hist_[i] = hs->hist[0][i];
+                if (zeta_hist_) zeta_hist_[i] = hs->hist[1][i];
+            }
+        } else if (cnt > 0) {
+            if (err_hist_)
+                HIP_TRY(hipMemcpyAsync(err_hist_, c_.err_hist(), sizeof(double) * cnt, hipMemcpyDeviceToHost, c_.s));
+            if (zeta_hist_)
+                HIP_TRY(hipMemcpyAsync(zeta_hist_, c_.zeta_hist(), sizeof(double) * cnt, hipMemcpyDeviceToHost, c_.s));
+            HIP_TRY(hipStreamSynchronize(c_.s));
+        }
         const int status = fin.stopped_by_tol ? RPCA_OK : RPCA_MAXITER;
         if (trace_on()) {
             std::vector<double> eh((size_t)n), zh((size_t)n);

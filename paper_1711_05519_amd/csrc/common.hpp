@@ -65,10 +65,6 @@ struct BodyRecord {
     double err;          // err of the state the body started from (loop bodies)
 };
 constexpr int BODY_RING = 8;
-// One per call in flight on a device (a pool in mapped, coherent host memory).
-struct HostStatus {
-    BodyRecord body[BODY_RING];
-};
 
 // Control block at the start of the workspace (device memory).
 struct Ctrl {
@@ -107,6 +103,16 @@ struct Ctrl {
     int32_t single;      // 1: D and the streamed factors are FP32
     int32_t nonfinite;   // 1: ||D||_F^2 was zero or not finite (bad input);
                          // 2: a later residual sum was not finite (bad state or breakdown)
+};
+
+// Leading entries of the err and zeta histories that a solve's last kernel
+// copies into its status slot; a longer history is read with two copies.
+constexpr int PUBLISH_HIST = 128;
+// One per call in flight on a device (a pool in mapped, coherent host memory).
+struct HostStatus {
+    BodyRecord body[BODY_RING];
+    Ctrl fin;                        // control block at the end of a solve
+    double hist[2][PUBLISH_HIST];    // err_0.., zeta_0.. at the end of a solve
 };
 
 // Small FP64 matrices shared between kernels (all K x K, row-major, ld = KMAX).

@@ -140,6 +140,8 @@ hipError_t launch_basis(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_start(const PanelArgs& a, int K, int dtype, hipStream_t s);
 hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, int batch, int64_t slab, hipStream_t s);
 hipError_t launch_enter_loop(Ctrl* ctrl, int batch, int64_t slab, hipStream_t s);
+hipError_t launch_publish(const Ctrl* ctrl, const double* err_hist, const double* zeta_hist, int hist_n,
+                          HostStatus* dst, hipStream_t s);
 hipError_t launch_slab_copy(void* slab0, int64_t slab, void* flat, int64_t pitch, int64_t bytes, int count,
                             int to_slabs, hipStream_t s);
 hipError_t launch_relax(const RelaxArgs& a, int dtype, hipStream_t s);

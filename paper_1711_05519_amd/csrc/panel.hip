@@ -971,6 +971,26 @@ __global__ void k_enter_loop(Ctrl* ctrl_, int64_t slab) {
     }
 }
 
+// End of a solve: copies the control block and the leading hist_n entries of
+// the err and zeta histories (at most k + 1 of them) into the call's status
+// slot in mapped host memory, so that the host reads them after one stream
+// synchronisation instead of three copies.
+__global__ void k_publish(const Ctrl* ctrl, const double* err_hist, const double* zeta_hist, int hist_n,
+                          HostStatus* dst) {
+    constexpr int CW = (int)(sizeof(Ctrl) / 4);
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(ctrl);
+    uint32_t* out = reinterpret_cast<uint32_t*>(&dst->fin);
+    for (int i = threadIdx.x; i < CW; i += blockDim.x) out[i] = src[i];
+    int n = ctrl->k + 1;
+    if (n > hist_n) n = hist_n;
+    if (n > PUBLISH_HIST) n = PUBLISH_HIST;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        dst->hist[0][i] = err_hist[i];
+        dst->hist[1][i] = zeta_hist[i];
+    }
+    __threadfence_system();
+}
+
 // Copies `bytes` (a multiple of 4) between each instance of a batch (instance
 // blockIdx.x at slab0 + blockIdx.x * slab) and row blockIdx.x of a flat array
 // (pitch bytes apart): to_slabs 1 writes the instances, 0 reads them.
@@ -1041,6 +1061,13 @@ hipError_t launch_setup(Ctrl* ctrl, const Ctrl& init, int batch, int64_t slab, h
 
 hipError_t launch_enter_loop(Ctrl* ctrl, int batch, int64_t slab, hipStream_t s) {
     hipLaunchKernelGGL(k_enter_loop, dim3(1, batch > 1 ? (unsigned)batch : 1u), dim3(64), 0, s, ctrl, slab);
+    return hipGetLastError();
+}
+
+hipError_t launch_publish(const Ctrl* ctrl, const double* err_hist, const double* zeta_hist, int hist_n,
+                          HostStatus* dst, hipStream_t s) {
+    if (!dst || hist_n < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(128), 0, s, ctrl, err_hist, zeta_hist, hist_n, dst);
     return hipGetLastError();
 }
 

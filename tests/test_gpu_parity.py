@@ -259,6 +259,37 @@ def test_max_iter_status():
     assert info.status == R.RPCA_MAXITER and info.iterations == 3
 
 
+def test_histories_short_and_long():
+    """The last kernel of a solve copies the control block and the leading 128
+    entries of both histories into mapped host memory; a longer history is
+    read with copies. A slow threshold decay (gamma = 0.9) and an unreachable
+    tol run 140 iterations (141 entries); the same solve capped at 100
+    iterations must give the same leading entries bit for bit, and both follow
+    the FP64 oracle while err is well above the rounding level."""
+    x = I.gaussian_instance(200, 180, 3, 0.1, 1.0, seed=6)
+    say("histories: 200x180 r=3 gamma=0.9, 140 and 100 iterations")
+    D = dev(x.D, torch.float64)
+    run = {}
+    for it in (140, 100):
+        sv = R.Solver(D, x.r, x.beta, x.beta_init, 0.9, x.mu_in, tol=1e-300, max_iter=it, seed=7)
+        run[it] = sv.solve()
+        info = run[it]
+        assert info.status == R.RPCA_MAXITER and info.iterations == it
+        assert len(info.err_hist) == len(info.zeta_hist) == it + 1
+        assert info.err_hist[-1] == info.err
+    a, b = run[140], run[100]
+    assert a.err_hist[:101] == b.err_hist and a.zeta_hist[:101] == b.zeta_hist
+    p = O.Params(r=x.r, beta=x.beta, beta_init=x.beta_init, gamma=0.9, mu=x.mu_in, tol=1e-300, max_iter=140)
+    ref = O.solve(x.D, p)
+    assert ref.iterations == 140
+    eo = np.asarray(ref.err_hist)
+    above = eo > 1e-8
+    say(f"  {int(above.sum())} entries above 1e-8; err_140 {a.err:.2e} (oracle {eo[-1]:.2e})")
+    np.testing.assert_allclose(np.asarray(a.err_hist)[above], eo[above], rtol=1e-6)
+    np.testing.assert_allclose(a.zeta_hist[:20], ref.zeta_hist[:20], rtol=1e-8, atol=2e-8 * ref.zeta_hist[1] / 0.9)
+    assert a.err < 1e-12
+
+
 # ---------------------------------------------------------- edge cases ----
 
 def test_unaligned_leading_dimension_matches_contiguous():
