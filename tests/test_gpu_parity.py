@@ -290,6 +290,30 @@ def test_histories_short_and_long():
     assert a.err < 1e-12
 
 
+def test_history_cap_and_null_histories():
+    """hist_cap below the iteration count: exactly hist_cap entries are
+    written (the rest of the caller's arrays stays untouched) and equal the
+    full histories' leading entries; null histories are accepted."""
+    import ctypes
+    x = I.gaussian_instance(300, 260, 3, 0.1, 1.0, seed=8)
+    say("history cap: 300x260 r=3")
+    sv = solver(x, torch.float32, tol=1e-5)
+    full = sv.solve()
+    assert full.iterations >= 5
+    lib = R._lib()
+    for cap in (3, 1, 0):
+        eh = (ctypes.c_double * 8)(*([-7.0] * 8))
+        zh = (ctypes.c_double * 8)(*([-7.0] * 8))
+        rc = lib.rpca_solve(R._ptr(sv.D), ctypes.byref(sv.params), ctypes.byref(sv.state), eh, zh, cap,
+                            *R._ws(sv.ws), R._stream(None))
+        assert rc == R.RPCA_OK and sv.state.k == full.iterations
+        assert list(eh[:cap]) == full.err_hist[:cap] and list(zh[:cap]) == full.zeta_hist[:cap]
+        assert list(eh[cap:]) == [-7.0] * (8 - cap) and list(zh[cap:]) == [-7.0] * (8 - cap)
+    rc = lib.rpca_solve(R._ptr(sv.D), ctypes.byref(sv.params), ctypes.byref(sv.state), None, None, 8,
+                        *R._ws(sv.ws), R._stream(None))
+    assert rc == R.RPCA_OK and sv.state.k == full.iterations and sv.state.err == full.err
+
+
 # ---------------------------------------------------------- edge cases ----
 
 def test_unaligned_leading_dimension_matches_contiguous():
