@@ -334,7 +334,7 @@ Layout make_layout(const rpca_params* p) {
     L.n_rt_max = n_rt_for(m, L.n_ct, STREAM_MAX_SLOTS);
     L.gU = (m + PANEL_THREADS - 1) / PANEL_THREADS;
     L.gV = (n + PANEL_THREADS - 1) / PANEL_THREADS;
-    const int rpb = GATHER_THREADS / GATHER_SPLIT;
+    const int rpb = gather_threads_for(m, n) / GATHER_SPLIT;
     const int g_gather = (m + rpb - 1) / rpb + (n + rpb - 1) / rpb;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };

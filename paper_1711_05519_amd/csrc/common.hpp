@@ -17,7 +17,17 @@ constexpr int STREAM_CPL = 4;     // consecutive columns owned by one lane
 constexpr int STREAM_TN = WAVE * STREAM_CPL;   // columns per stream tile
 constexpr int PANEL_THREADS = 256;
 constexpr int GATHER_SPLIT = 8;   // adjacent lanes sharing one row in the gather kernel (<= 16)
-constexpr int GATHER_THREADS = 1024;
+constexpr int GATHER_THREADS = 1024;        // gather workgroup: 128 rows
+constexpr int GATHER_THREADS_SMALL = 512;   // gather workgroup for small problems: 64 rows
+constexpr int GATHER_SMALL_MAX_ROWS = 8192; // m + n up to which the small workgroup is used
+// Threads per workgroup of the gather kernel for an m x n problem. Halving the
+// rows per workgroup below m + n = 8192 spreads the small problems' partial
+// sums over twice as many CUs (2-3 % faster solves at m = n = 2000-3000, 7 %
+// for a batch of 2000 x 2000 instances); above, the last workgroup's sum over
+// the doubled number of partials costs more than that gains.
+__host__ __device__ constexpr int gather_threads_for(int64_t m, int64_t n) {
+    return m + n <= GATHER_SMALL_MAX_ROWS ? GATHER_THREADS_SMALL : GATHER_THREADS;
+}
 constexpr int GPART_STRIDE = 2 * KMAX * KMAX;   // doubles per workgroup partial slot
 // relaxed iteration (threshold training)
 constexpr int RX_KMAX = 10;        // largest rank of the relaxed iteration (3r <= 30 for the wave SVD)

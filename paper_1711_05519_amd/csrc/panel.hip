@@ -380,11 +380,11 @@ __device__ inline PanelArgs at_instance(const PanelArgs& a0) {
 // The last workgroup sums the per-workgroup partials with all its threads.
 // FP32 (gram_form): also the Grams of Y1 and Y2, and the whole 2K x 2K step in
 // the tail. FP64: only C* and C2; the complement kernel forms W explicitly.
-template <typename T, int K>
-__global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a_) {
+template <typename T, int K, int NT>
+__global__ __launch_bounds__(NT) void k_gather(PanelArgs a_) {
     PanelArgs a = at_instance(a_);
     using Acc = typename AccOf<T>::type;
-    constexpr int RPB = GATHER_THREADS / GATHER_SPLIT;   // rows per workgroup
+    constexpr int RPB = NT / GATHER_SPLIT;   // rows per workgroup
     constexpr bool GRAM = sizeof(T) == 4;
     Ctrl* ctrl = a.ctrl;
     // The gate is read here and tested once the tile sums are in LDS, so that
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a_) {
     }
     // BL^T V_f (U side) or AL^T U_f (V side) for the rank-K part, one entry
     // per thread, put into LDS with the tile sums
-    static_assert(K * K <= GATHER_THREADS, "one entry of the cross product per thread");
+    static_assert(K * K <= NT, "one entry of the cross product per thread");
     __shared__ double gk[K * K];
     double gkv = 0.0;
     if (a.lcorr && (int)threadIdx.x < K * K)
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a_) {
     constexpr int VW = 16 / (int)sizeof(Acc);
     constexpr int FB = RPB * K;
     constexpr int NV = FB / VW;
-    constexpr int NWG = GATHER_THREADS / NV;
+    constexpr int NWG = NT / NV;
     constexpr int LR = 8;
     static_assert(FB % VW == 0 && NWG >= 1, "tile block of the gather");
     typedef typename Vec16<Acc>::type VecT;
@@ -516,15 +516,15 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a_) {
     double* gp = a.gpart + (size_t)blockIdx.x * GPART_STRIDE;
     const bool writer = chunk == 0;   // y and f are zero unless this lane holds a valid row
     if (GRAM)   // U_f^T Y1 (V_f^T Y2) and Gram(Y1) (Gram(Y2))
-        rows_outer_sum2<K, RPB, GATHER_THREADS>(f, y, y, writer, slot, sa, shbuf + 2 * FB, sb, gp, gp + KMAX * KMAX);
+        rows_outer_sum2<K, RPB, NT>(f, y, y, writer, slot, sa, shbuf + 2 * FB, sb, gp, gp + KMAX * KMAX);
     else
-        rows_outer_sum<K, RPB, GATHER_THREADS>(f, y, writer, slot, sa, sb, gp);   // U_f^T Y1 or V_f^T Y2
+        rows_outer_sum<K, RPB, NT>(f, y, writer, slot, sa, sb, gp);   // U_f^T Y1 or V_f^T Y2
     if (!last_block_arrives(&ctrl->cnt[CNT_GATHER], &flag)) return;
 
     // ---- last workgroup: all threads sum the partials, then one wave ----
     __shared__ double sums[4 * K * K], ru[K * K], rv[K * K], cs[K * K], c2[K * K], tmp[K * K], tmp2[K * K];
     __shared__ double g1[K * K], g2[K * K];
-    __shared__ double part[GATHER_THREADS], rsum[2];
+    __shared__ double part[NT], rsum[2];
     double* craw = sums;              // U_f^T Y1
     double* craw2 = sums + K * K;     // V_f^T Y2
     double* gy1 = sums + 2 * K * K;   // Gram(Y1)
@@ -534,7 +534,7 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a_) {
     // the residual tiles and R_U^{-1}, R_V^{-1} are loaded before the partials
     // are summed, so that the three loads overlap
     double rv_[RESID_LD], rw_[RESID_LD];
-    block_resid_fetch<GATHER_THREADS>(a.resid, a.n_tiles, sigma_stage, rv_, rw_);
+    block_resid_fetch<NT>(a.resid, a.n_tiles, sigma_stage, rv_, rw_);
     double ru_pre[w_per_lane<K>()], rv_pre[w_per_lane<K>()];
     if (threadIdx.x < WAVE) {
         w_fetch<K>(a.small->RUinv, ru_pre);
@@ -552,24 +552,24 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PanelArgs a_) {
     // layer transposed, see w_mlp): loaded with this phase's other loads,
     // stored before the barrier of block_resid.
     __shared__ float th_s[GRAM ? MLP_PARAMS : 1];
-    constexpr int TPT = GRAM ? (MLP_PARAMS + GATHER_THREADS - 1) / GATHER_THREADS : 1;
+    constexpr int TPT = GRAM ? (MLP_PARAMS + NT - 1) / NT : 1;
     float thv[TPT];
 #pragma unroll
     for (int u = 0; u < TPT; ++u) {
-        const int e = threadIdx.x + u * GATHER_THREADS;
+        const int e = threadIdx.x + u * NT;
         thv[u] = (GRAM && a.mlp && e < MLP_PARAMS) ? a.mlp[e] : 0.f;
     }
-    block_sum_partials<K * K, GRAM ? 4 : 2, GATHER_THREADS>(a.gpart, gU, gV, sums, part);
+    block_sum_partials<K * K, GRAM ? 4 : 2, NT>(a.gpart, gU, gV, sums, part);
 #pragma unroll
     for (int u = 0; u < TPT; ++u) {
-        const int e = threadIdx.x + u * GATHER_THREADS;
+        const int e = threadIdx.x + u * NT;
         if (GRAM && a.mlp && e < MLP_PARAMS) {
             constexpr int OW2 = MLP_H * MLP_IN + MLP_H;
             const int w = e - OW2;
             th_s[(w >= 0 && w < MLP_H * MLP_H) ? OW2 + (w % MLP_H) * MLP_H + w / MLP_H : e] = thv[u];
         }
     }
-    block_resid<GATHER_THREADS>(a.resid, a.n_tiles, sigma_stage, rv_, rw_, part, rsum);
+    block_resid<NT>(a.resid, a.n_tiles, sigma_stage, rv_, rw_, part, rsum);
     if (threadIdx.x >= WAVE) return;
     const int lane = lane_id();
     if (lane < CW) reinterpret_cast<uint32_t*>(&cl)[lane] = cword;
@@ -1032,12 +1032,25 @@ __global__ void k_convert(const double* __restrict__ src, T* __restrict__ dst, i
         return hipGetLastError();                                                                \
     }
 
-constexpr int GATHER_RPB = GATHER_THREADS / GATHER_SPLIT;
+// The gather's workgroup size depends on the shape only (gather_threads_for),
+// so a batch and a single solve of one shape sum in the same order.
+#define RPCA_GATHER_F(KK) hipLaunchKernelGGL((k_gather<float, KK, NTG>), grid, block, 0, s, a)
+#define RPCA_GATHER_D(KK) hipLaunchKernelGGL((k_gather<double, KK, NTG>), grid, block, 0, s, a)
+template <int NTG>
+hipError_t launch_gather_nt(const PanelArgs& a, int K, int dtype, hipStream_t s) {
+    constexpr int rpb = NTG / GATHER_SPLIT;
+    const dim3 grid((unsigned)((a.m + rpb - 1) / rpb + (a.n + rpb - 1) / rpb), a.batch > 1 ? (unsigned)a.batch : 1u),
+        block(NTG);
+    if (dtype == 1) { RPCA_K_SWITCH(RPCA_GATHER_F) } else { RPCA_K_SWITCH(RPCA_GATHER_D) }
+    return hipGetLastError();
+}
+#undef RPCA_GATHER_F
+#undef RPCA_GATHER_D
 
-#define KFUN k_gather
-RPCA_PANEL_LAUNCHER(launch_gather, (unsigned)((a.m + GATHER_RPB - 1) / GATHER_RPB + (a.n + GATHER_RPB - 1) / GATHER_RPB),
-                    GATHER_THREADS)
-#undef KFUN
+hipError_t launch_gather(const PanelArgs& a, int K, int dtype, hipStream_t s) {
+    return gather_threads_for(a.m, a.n) == GATHER_THREADS_SMALL ? launch_gather_nt<GATHER_THREADS_SMALL>(a, K, dtype, s)
+                                                                : launch_gather_nt<GATHER_THREADS>(a, K, dtype, s);
+}
 #define KFUN k_complement
 RPCA_PANEL_LAUNCHER(launch_complement, (unsigned)(a.gU + a.gV), PANEL_THREADS)
 #undef KFUN
