@@ -241,10 +241,19 @@ template <typename X> __device__ inline X* moved(X* p, int64_t off) {
     return reinterpret_cast<X*>(reinterpret_cast<C*>(p) + off);
 }
 
-// The increment releases (agent scope) the workgroup's results; only the
-// last workgroup acquires, so the others skip the L2 invalidation a full
-// fence costs.
+// Last-workgroup election. The workgroup barrier orders the waves but does not
+// wait for their global stores to complete (only for their LDS operations),
+// and the increment's release (agent scope: write-back of this XCD's L2, then
+// the atomic) covers what has reached the L2 by then. So every wave first
+// waits until its own stores have completed, i.e. reached the L2; otherwise
+// a partial still in flight from another wave could miss the write-back, and
+// the last workgroup, on another XCD with its own L2, would read a stale
+// value. (A release fence in every wave would also do, at 16 L2 write-backs
+// per workgroup: 17 us more per loop body at m = n = 10^4.) Only the last
+// workgroup acquires, so the others skip the L2 invalidation a full fence
+// costs.
 __device__ inline bool last_block_arrives(uint32_t* counter, int* flag_smem) {
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);

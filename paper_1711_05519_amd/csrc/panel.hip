@@ -1033,7 +1033,7 @@ __global__ void k_convert(const double* __restrict__ src, T* __restrict__ dst, i
     }
 
 // The gather's workgroup size depends on the shape only (gather_threads_for),
-// so a batch and a single solve of one shape sum in the same order.
+// not on the number of instances of a batch.
 #define RPCA_GATHER_F(KK) hipLaunchKernelGGL((k_gather<float, KK, NTG>), grid, block, 0, s, a)
 #define RPCA_GATHER_D(KK) hipLaunchKernelGGL((k_gather<double, KK, NTG>), grid, block, 0, s, a)
 template <int NTG>

@@ -94,6 +94,24 @@ def test_batch_matches_single_solves_fp32(form):
         assert O.recovery_error(L, x.L) <= 1e-4
 
 
+def test_batch_matches_single_solves_above_the_gather_switch():
+    """m + n > 8192: the gather runs 1024-thread workgroups of 128 rows (the
+    instances above use the 64-row form)."""
+    xs, p = draw(4300, 4000, 3, 0.1, [41, 42, 43], 1e-5)
+    bs = batch_of(xs, p, torch.float32)
+    infos = bs.solve()
+    for i, (x, info) in enumerate(zip(xs, infos)):
+        sv, ref = single(x, p, torch.float32)
+        L = L_of(bs.U[i], bs.sigma[i], bs.V[i])
+        d = rel(L, L_of(sv.U, sv.sigma, sv.V))
+        say(f"4300 x 4000 instance {i}: {info.iterations}/{ref.iterations} iterations, rel L to the single solve {d:.2e}")
+        assert info.status == ref.status == R.RPCA_OK
+        assert info.iterations == ref.iterations and info.init_passes == ref.init_passes
+        np.testing.assert_allclose(info.err_hist, ref.err_hist, rtol=1e-3)
+        assert d <= 1e-5
+        assert O.recovery_error(L, x.L) <= 1e-4
+
+
 def test_batch_isolates_failing_instances():
     xs, p = draw(200, 180, 2, 0.1, [41, 42, 43, 44], 1e-5)
     D = torch.stack([torch.as_tensor(x.D, dtype=torch.float32) for x in xs])

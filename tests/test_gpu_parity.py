@@ -172,6 +172,9 @@ def _oracle_state_after(x, D, p, k):
     (400, 300, 4, 0.1, 1.0, 5, True),
     (333, 517, 3, 0.2, 2.0, 3, True),
     (300, 300, 5, 0.1, 1.0, 6, False),
+    # either side of m + n = 8192, where the gather switches from 64-row to 128-row workgroups
+    (7992, 200, 3, 0.1, 1.0, 3, True),
+    (7993, 200, 3, 0.1, 1.0, 3, True),
 ])
 def test_step_from_oracle_state(dtype, m, n, r, alpha, c, k, trim):
     say(f"step dtype={dtype} m={m} n={n} r={r} k={k} trim={trim}")
