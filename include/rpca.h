@@ -233,8 +233,11 @@ int rpca_solve_many(int32_t count, const void *const *D, const rpca_params *cons
  * instance i, may be NULL) entries 0..st[i].k; status[i] the status
  * rpca_solve would return. Returns RPCA_OK or the first negative instance
  * status; RPCA_EINVAL for bad arguments (1 <= count <= RPCA_BATCH_MAX). Returns
- * after the device work is done. Batched calls on one device run one at a time
- * (they share a small buffer of mapped host memory that the library keeps). */
+ * after the device work is done. Up to 4 batched calls run on one device at
+ * once (from different host threads, each on its own stream: a pass of one
+ * batch then overlaps the latency-bound kernels of another); each holds one of
+ * 4 small buffers of mapped host memory that the library keeps per device, and
+ * a fifth call waits for the first buffer. */
 typedef struct rpca_batch_layout {
     size_t slab_bytes;               /* bytes per instance (a multiple of 256)         */
     size_t off_D, off_U, off_V, off_sigma, off_ws;   /* offsets inside a slab          */

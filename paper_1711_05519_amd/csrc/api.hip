@@ -56,6 +56,14 @@ constexpr int MAX_DEVICES = 64;
 // device that runs a queue of bodies (rpca_init, rpca_solve).
 constexpr int STATUS_SLOTS = 32;
 
+constexpr int BATCH_BUFS = 4;
+struct BatchBuf {
+    std::mutex mutex;
+    void* host = nullptr;
+    void* dev = nullptr;
+    size_t bytes = 0;
+};
+
 struct DeviceInfo {
     bool checked = false;
     bool ok = false;
@@ -65,12 +73,11 @@ struct DeviceInfo {
     HostStatus* status_dev = nullptr;
     uint32_t slots_used = 0;             // bit i: slot i belongs to a call (g_dev_mutex)
     void* scratch = nullptr;             // this device's copy of `scratch` (rpca_step_noalloc)
-    // mapped host buffer of rpca_solve_batch, grown on demand and kept; one
-    // batched call at a time per device holds batch_mutex while it uses it
-    std::mutex batch_mutex;
-    void* batch_host = nullptr;
-    void* batch_dev = nullptr;
-    size_t batch_bytes = 0;
+    // mapped host buffers of rpca_solve_batch, grown on demand and kept; a
+    // batched call holds one (its mutex) while it runs, so up to BATCH_BUFS
+    // batched calls (from different host threads, on different streams) run
+    // on a device at once
+    BatchBuf batch[BATCH_BUFS];
 };
 std::mutex g_dev_mutex;
 DeviceInfo g_dev[MAX_DEVICES];
@@ -1153,15 +1160,29 @@ int rpca_batch_layout_of(const rpca_params* p, rpca_batch_layout* out) {
 // and reads all control blocks in between (one strided copy).
 static_assert(sizeof(Ctrl) % 8 == 0, "control blocks are copied in 4-byte words, rows stay 8-byte aligned");
 
-// The device's mapped, coherent host buffer for batched calls, at least
-// `bytes` long (batch_mutex held by the caller). Returns false if it cannot be
-// allocated.
-bool batch_buffer(DeviceInfo* d, size_t bytes) {
-    if (d->batch_bytes >= bytes) return true;
-    if (d->batch_host) {
-        (void)hipHostFree(d->batch_host);
-        d->batch_host = d->batch_dev = nullptr;
-        d->batch_bytes = 0;
+// One of the device's mapped, coherent host buffers for batched calls, locked
+// for the caller: the first one free, else (every one in use) the first, once
+// its call has ended.
+std::unique_lock<std::mutex> take_batch_buffer(DeviceInfo* d, BatchBuf** out) {
+    for (int i = 0; i < BATCH_BUFS; ++i) {
+        std::unique_lock<std::mutex> lock(d->batch[i].mutex, std::try_to_lock);
+        if (lock.owns_lock()) {
+            *out = &d->batch[i];
+            return lock;
+        }
+    }
+    *out = &d->batch[0];
+    return std::unique_lock<std::mutex>(d->batch[0].mutex);
+}
+
+// Grows a batch buffer (its mutex held by the caller) to at least `bytes`.
+// Returns false if it cannot be allocated.
+bool batch_buffer(BatchBuf* b, size_t bytes) {
+    if (b->bytes >= bytes) return true;
+    if (b->host) {
+        (void)hipHostFree(b->host);
+        b->host = b->dev = nullptr;
+        b->bytes = 0;
     }
     void* h = nullptr;
     const size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
@@ -1171,9 +1192,9 @@ bool batch_buffer(DeviceInfo* d, size_t bytes) {
         (void)hipHostFree(h);
         return false;
     }
-    d->batch_host = h;
-    d->batch_dev = dp;
-    d->batch_bytes = want;
+    b->host = h;
+    b->dev = dp;
+    b->bytes = want;
     return true;
 }
 
@@ -1213,13 +1234,14 @@ int rpca_solve_batch(int32_t count, void* slabs, const rpca_params* params, rpca
     // kernel (one row per instance)
     const int cnt_h = hist_cap < p->max_iter + 1 ? hist_cap : p->max_iter + 1;
     const size_t row = sizeof(Ctrl) + 2 * sizeof(double) * (size_t)(cnt_h > 0 ? cnt_h : 0);
-    std::lock_guard<std::mutex> hold(c.dev->batch_mutex);
-    if (!batch_buffer(c.dev, row * (size_t)count)) {
+    BatchBuf* bb = nullptr;
+    const std::unique_lock<std::mutex> hold = take_batch_buffer(c.dev, &bb);
+    if (!batch_buffer(bb, row * (size_t)count)) {
         g_last_hip_error = (int)hipErrorOutOfMemory;
         return RPCA_EHIP;
     }
-    void* const hb_dev = c.dev->batch_dev;
-    Ctrl* ctl = reinterpret_cast<Ctrl*>(c.dev->batch_host);
+    void* const hb_dev = bb->dev;
+    Ctrl* ctl = reinterpret_cast<Ctrl*>(bb->host);
     // (the host spins on the stream instead of a blocking wait, which can put
     // the thread to sleep for much longer than a few bodies take)
     auto read_all = [&]() -> int {

@@ -19,7 +19,7 @@ library's solver; the comparison systems are not part of this package).
       threshold: 2000 x 2000, r = 5 .. 10, alpha 0.05 .. 0.3, FP32): solves
       one after another against rpca_solve_many on 4, 8 and 16 streams and
       against rpca_solve_batch (one batch per rank, every launch covering
-      all instances of the batch).
+      all instances of the batch), one batch after another and on 3 streams.
   python -m paper_1711_05519_amd.experiments video
       Video-shaped workload (144 x 176 pixels x 2000 frames, r = 2, the
       stand-in for the background-subtraction data): time, iterations and the
@@ -196,6 +196,22 @@ def many(args):
             its_b[i] = info.iterations
     emit(experiment="many", mode=f"batched ({len(batches)} batches, one per rank)", count=args.count,
          seconds=t, per_solve=t / args.count, iterations=sum(its_b), speedup=t_seq / t, same_iterations=its_b == its,
+         bytes_of_D=args.count * xs[0].m * xs[0].n * 4)
+    # the same batches on 3 streams from 3 host threads (solve_batches)
+    torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
+    t0 = time.perf_counter()
+    res = R.solve_batches([bs for _, bs in batches], n_streams=3)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    gc.enable()
+    its_c = [0] * args.count
+    for (idx, _), infos in zip(batches, res):
+        for i, info in zip(idx, infos):
+            its_c[i] = info.iterations
+    emit(experiment="many", mode=f"batched ({len(batches)} batches) on 3 streams", count=args.count,
+         seconds=t, per_solve=t / args.count, iterations=sum(its_c), speedup=t_seq / t, same_iterations=its_c == its,
          bytes_of_D=args.count * xs[0].m * xs[0].n * 4)
 
 

@@ -608,6 +608,50 @@ def solve_many(solvers, n_streams: int = 8) -> list:
     return out
 
 
+RPCA_BATCH_BUFS = 4   # batched calls that run on one device at once
+
+
+def solve_batches(batches, n_streams: int = 3) -> list:
+    """Solves several BatchSolver objects (batches of different shapes or
+    ranks) concurrently: n_streams host threads, each on its own new stream,
+    take the batches in order of decreasing size (instances x m x n x r), each
+    thread the batch that keeps its queue shortest. One batch's streaming pass
+    then overlaps the latency-bound kernels of another. Returns each batch's
+    list of SolveInfo, in the order of `batches`; results are those of
+    solving the batches one after another."""
+    import threading
+    n_streams = max(1, min(n_streams, RPCA_BATCH_BUFS, len(batches)))
+    if not batches:
+        return []
+    dev = batches[0].D.device
+    torch.cuda.current_stream(dev).synchronize()   # slabs written on the current stream are complete
+    cost = [bs.count * bs.params.m * bs.params.n * bs.params.r for bs in batches]
+    queues, load = [[] for _ in range(n_streams)], [0] * n_streams
+    for i in sorted(range(len(batches)), key=lambda i: -cost[i]):
+        q = min(range(n_streams), key=lambda k: load[k])
+        queues[q].append(i)
+        load[q] += cost[i]
+    streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
+    out, errors = [None] * len(batches), []
+
+    def work(k):
+        try:
+            with torch.cuda.device(dev), torch.cuda.stream(streams[k]):
+                for i in queues[k]:
+                    out[i] = batches[i].solve()
+        except BaseException as e:   # re-raised in the calling thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(n_streams)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    if errors:
+        raise errors[0]
+    return out
+
+
 class UnrolledRelaxed(torch.autograd.Function):
     """loss = UnrolledRelaxed.apply(zetas, U0, sigma0, V0, solver, P, Q, taus, weights):
     K = len(zetas) relaxed iterations of `solver` from L_0 = U0 diag(sigma0) V0^T

@@ -112,6 +112,32 @@ def test_batch_matches_single_solves_above_the_gather_switch():
         assert O.recovery_error(L, x.L) <= 1e-4
 
 
+def test_concurrent_batches_match_sequential_ones():
+    """Five batches of different shapes and ranks on four streams from four
+    host threads (solve_batches; every buffer of the library's pool in use,
+    the fifth batch waits for one) give exactly the results of solving them
+    one after another."""
+    specs = [(300, 260, 3, [51, 52, 53, 54]), (400, 350, 4, [55, 56, 57]), (256, 300, 2, [58, 59, 60, 61, 62]),
+             (333, 333, 5, [63, 64]), (280, 240, 3, [65, 66, 67])]
+    batches = []
+    for m, n, r, seeds in specs:
+        xs, p = draw(m, n, r, 0.1, seeds, 1e-5)
+        batches.append(batch_of(xs, p, torch.float32))
+    seq = []
+    for bs in batches:
+        infos = bs.solve()
+        seq.append((infos, bs.U.clone(), bs.sigma.clone(), bs.V.clone()))
+    for b in batches:   # clear the iterates, so that the concurrent solves must write them
+        b.U.zero_(); b.V.zero_(); b.sigma.zero_()
+    conc = R.solve_batches(batches, n_streams=4)
+    torch.cuda.synchronize()
+    for j, (bs, (infos, U, s, V), got) in enumerate(zip(batches, seq, conc)):
+        say(f"batch {j}: {[i.iterations for i in got]} iterations")
+        assert [(i.status, i.iterations, i.err_hist, i.zeta_hist) for i in got] == \
+               [(i.status, i.iterations, i.err_hist, i.zeta_hist) for i in infos]
+        assert torch.equal(bs.U, U) and torch.equal(bs.sigma, s) and torch.equal(bs.V, V)
+
+
 def test_batch_isolates_failing_instances():
     xs, p = draw(200, 180, 2, 0.1, [41, 42, 43, 44], 1e-5)
     D = torch.stack([torch.as_tensor(x.D, dtype=torch.float32) for x in xs])
