@@ -114,9 +114,9 @@ def test_batch_matches_single_solves_above_the_gather_switch():
 
 def test_concurrent_batches_match_sequential_ones():
     """Five batches of different shapes and ranks on four streams from four
-    host threads (solve_batches; every buffer of the library's pool in use,
-    the fifth batch waits for one) give exactly the results of solving them
-    one after another."""
+    host threads (solve_batches: all four buffers of the library's pool in
+    use at once, one thread runs two batches) give exactly the results of
+    solving them one after another."""
     specs = [(300, 260, 3, [51, 52, 53, 54]), (400, 350, 4, [55, 56, 57]), (256, 300, 2, [58, 59, 60, 61, 62]),
              (333, 333, 5, [63, 64]), (280, 240, 3, [65, 66, 67])]
     batches = []
