@@ -138,6 +138,37 @@ def test_concurrent_batches_match_sequential_ones():
         assert torch.equal(bs.U, U) and torch.equal(bs.sigma, s) and torch.equal(bs.V, V)
 
 
+def test_more_concurrent_batch_calls_than_buffers():
+    """Six host threads each call rpca_solve_batch on a stream of its own: four
+    calls hold the library's four buffers, the others wait for the first one
+    and then run; every batch gets the results of a sequential solve."""
+    import threading
+    batches = []
+    for j in range(6):
+        xs, p = draw(260 + 10 * j, 240, 2 + j % 3, 0.1, [81 + 3 * j, 82 + 3 * j], 1e-5)
+        batches.append(batch_of(xs, p, torch.float32))
+    seq = [[(i.iterations, i.err_hist) for i in bs.solve()] for bs in batches]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in batches]
+    got, errors = [None] * len(batches), []
+
+    def work(j):
+        try:
+            with torch.cuda.stream(streams[j]):
+                got[j] = [(i.iterations, i.err_hist) for i in batches[j].solve()]
+        except BaseException as e:
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(j,)) for j in range(len(batches))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads), "a batched call did not return"
+    assert not errors, errors
+    assert got == seq
+
+
 def test_repeated_solves_are_identical():
     """Every cross-workgroup sum is summed in a fixed order by the last
     workgroup, after every wave's partials have reached memory: repeated
