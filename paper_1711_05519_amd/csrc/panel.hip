@@ -335,7 +335,8 @@ __device__ __forceinline__ void w_svd_tail(const PanelArgs& a, Ctrl* ctrl, const
 
 // ---- kernel 1: gather partial products, C*, residual, stopping rule ----------
 //
-// 1024 threads, 128 rows per workgroup (GATHER_SPLIT threads per row slot,
+// NT threads, NT / 8 rows per workgroup (1024 and 128, or 512 and 64 for
+// small problems: gather_threads_for; GATHER_SPLIT threads per row slot,
 // the first of which holds the row): the per-tile partials of the
 // workgroup's rows are summed with 16-byte loads of whole tile blocks, then
 // the row products U_f^T Y1 (and Grams) are formed as workgroup partials.
