@@ -618,12 +618,14 @@ def solve_batches(batches, n_streams: int = 3) -> list:
     thread the batch that keeps its queue shortest. One batch's streaming pass
     then overlaps the latency-bound kernels of another. Returns each batch's
     list of SolveInfo, in the order of `batches`; results are those of
-    solving the batches one after another."""
+    solving the batches one after another. All batches are on one device."""
     import threading
     n_streams = max(1, min(n_streams, RPCA_BATCH_BUFS, len(batches)))
     if not batches:
         return []
     dev = batches[0].D.device
+    if any(bs.D.device != dev for bs in batches):
+        raise ValueError("solve_batches: every batch must be on one device")
     torch.cuda.current_stream(dev).synchronize()   # slabs written on the current stream are complete
     cost = [bs.count * bs.params.m * bs.params.n * bs.params.r for bs in batches]
     queues, load = [[] for _ in range(n_streams)], [0] * n_streams
